@@ -1,0 +1,805 @@
+// gfx950 kernels of the GRMHD hot path and the C ABI declared in grmhd.h.
+//
+// Kernels
+//   k_prim2con  one thread per interior cell (Eqs. (p2c1)-(p2c4)).
+//   k_con2prim  one thread per interior cell: 3D Newton, Newman-Hamlin fallback,
+//               atmosphere (Sec. II C, RHS step 1).
+//   k_stage     one workgroup per TX x TY x TZ = 256-cell tile: for each
+//               direction every thread reconstructs and solves the Riemann
+//               problem on its cell's low face (and the tile's high-boundary
+//               faces), fluxes are exchanged through LDS, and the divergence,
+//               the source terms and the SSPRK stage combine are fused, so no
+//               face quantity ever reaches HBM (Sec. II C, RHS steps 2-4).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "grmhd.h"
+#include "grmhd_device.h"
+
+using namespace gk;
+
+namespace {
+
+constexpr uint64_t TABLE_MAGIC = 0x47524d4844544231ull;  // "GRMHDTB1"
+
+// tile shapes of the stage kernel (TX * TY * TZ = 256)
+constexpr int TILE_X[NTILE] = {16, 8, 64};
+constexpr int TILE_Y[NTILE] = {4, 8, 2};
+constexpr int TILE_Z[NTILE] = {4, 4, 2};
+
+struct StageArgs {
+  Table tab;
+  int tile;
+  const double* __restrict__ P;
+  const double* __restrict__ Us;
+  const double* __restrict__ Un;
+  double* __restrict__ Uout;
+  const double* __restrict__ alpha;
+  const double* __restrict__ beta;
+  const double* __restrict__ gamma;
+  int64_t cs, vs;
+  double cstage, dt;
+  int32_t mode;  // 0: Uout = dU/dt; 1: Uout = Un + c ((Us - Un) + dt dU/dt)
+  KPhys ph;
+  double* max_rate;
+};
+
+struct CellArgs {
+  Table tab;
+  double* U;
+  double* P;
+  double* ckpt;  // nullable copy of U after con2prim
+  int32_t* status;
+  unsigned long long* n_fail;
+  const double* __restrict__ gamma;
+  int64_t cs, vs;
+  KPhys ph;
+};
+
+__device__ __forceinline__ void block_max_atomic(double v, double* target) {
+  // v >= 0: the IEEE bit pattern orders like an unsigned integer
+  __shared__ double red[4];
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    if (m > 0.0) atomicMax(reinterpret_cast<unsigned long long*>(target), (unsigned long long)__double_as_longlong(m));
+  }
+}
+
+// ---------------------------------------------------------------- stage kernel
+
+template <int D, int RECON, typename R, bool SHIFT>
+__device__ __forceinline__ void face_flux(const StageArgs& a, const KBox& bx, const double* __restrict__ Pb,
+                                          const double* __restrict__ alb, const double* __restrict__ beb,
+                                          const double* __restrict__ gab, int i, int j, int k, double F[8],
+                                          double& rate) {
+  const int ng = bx.ng;
+  const int c = (D == 0) ? i : (D == 1 ? j : k);
+  const int nD = bx.n[D];
+  const int sD = (D == 0) ? 1 : (D == 1 ? bx.NX : bx.NXY);
+  // storage index of the cell with coordinate 0 along D on this grid line
+  const int base = (D == 0)   ? ((k + ng) * (bx.NXY / bx.NX) + (j + ng)) * bx.NX + ng
+                   : (D == 1) ? (k + ng) * bx.NXY + ng * bx.NX + (i + ng)
+                              : ng * bx.NXY + (j + ng) * bx.NX + (i + ng);
+  constexpr int O0 = (RECON == GRMHD_RECON_MINMOD) ? 1 : 0;  // minmod reads cells c-2 .. c+1
+  constexpr int O1 = (RECON == GRMHD_RECON_MINMOD) ? 5 : 6;
+  int idx[6];
+#pragma unroll
+  for (int o = O0; o < O1; ++o) {
+    const int m = c + o - 3;
+    const int mm = (m < 0) ? bx.mlo[D][m + 3] : (m >= nD ? bx.mhi[D][m - nD] : m);
+    idx[o] = base + mm * sD;
+  }
+  R PL[8], PR[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const double* __restrict__ f = Pb + q * a.cs;
+    R s[6];
+#pragma unroll
+    for (int o = O0; o < O1; ++o) s[o] = (R)f[idx[o]];
+    if (RECON == GRMHD_RECON_MINMOD) {
+      PL[q] = s[2] + R(0.5) * minmod(s[2] - s[1], s[3] - s[2]);
+      PR[q] = s[3] - R(0.5) * minmod(s[3] - s[2], s[4] - s[3]);
+    } else {
+      const bool z = (RECON == GRMHD_RECON_WENOZ);
+      const R eps = (R)(z ? a.ph.wenoz_eps : a.ph.weno_eps);
+      if (z) {
+        PL[q] = weno5<true>(s[0], s[1], s[2], s[3], s[4], eps, a.ph.wenoz_p);
+        PR[q] = weno5<true>(s[5], s[4], s[3], s[2], s[1], eps, a.ph.wenoz_p);
+      } else {
+        PL[q] = weno5<false>(s[0], s[1], s[2], s[3], s[4], eps, 1);
+        PR[q] = weno5<false>(s[5], s[4], s[3], s[2], s[1], eps, 1);
+      }
+    }
+  }
+  // face metric from the 4 vertices of the face
+  const int vb = ((k + ng) * (bx.VXY / bx.VX) + (j + ng)) * bx.VX + (i + ng);
+  constexpr int A = (D + 1) % 3, B = (D + 2) % 3;
+  const int sa = (A == 0) ? 1 : (A == 1 ? bx.VX : bx.VXY);
+  const int sb = (B == 0) ? 1 : (B == 1 ? bx.VX : bx.VXY);
+  FaceMetric<R> m;
+  face_metric<D, SHIFT, R>(alb, beb, gab, a.vs, vb, sa, sb, m);
+  // positivity: fall back to the cell values on a side that is not physical
+  SideState<R> sL, sR;
+  side_v2(m, PL, sL);
+  side_v2(m, PR, sR);
+  if (!side_ok(PL, sL.v2)) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) PL[q] = (R)Pb[q * a.cs + idx[2]];
+    side_v2(m, PL, sL);
+  }
+  if (!side_ok(PR, sR.v2)) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) PR[q] = (R)Pb[q * a.cs + idx[3]];
+    side_v2(m, PR, sR);
+  }
+  const R gm1 = (R)a.ph.gm1, gam = (R)a.ph.gam;
+  side_rest(m, PL, gm1, sL);
+  side_rest(m, PR, gm1, sR);
+  R Fs[8], xp, xm;
+  hlle<D>(m, PL, sL, PR, sR, gam, Fs, xp, xm);
+#pragma unroll
+  for (int q = 0; q < 8; ++q) F[q] = (double)Fs[q];
+  rate = fmax(rate, fmax((double)xp, -(double)xm) * bx.inv_dx[D]);
+}
+
+template <int TX, int TY, int TZ> struct TileGeo {
+  static constexpr int SX[3] = {TX + 1, TX, TX};
+  static constexpr int SY[3] = {TY, TY + 1, TY};
+  static constexpr int SZ[3] = {TZ, TZ, TZ + 1};
+  static constexpr int slots(int d) { return SX[d] * SY[d] * SZ[d]; }
+  static constexpr int maxslots() {
+    return std::max(slots(0), std::max(slots(1), slots(2)));
+  }
+};
+
+template <int D, int RECON, typename R, bool SHIFT, int TX, int TY, int TZ>
+__device__ __forceinline__ void direction_phase(const StageArgs& a, const KBox& bx, const double* __restrict__ Pb,
+                                                const double* __restrict__ alb, const double* __restrict__ beb,
+                                                const double* __restrict__ gab, const int org[3], const int l[3],
+                                                bool valid, double (*sF)[TileGeo<TX, TY, TZ>::maxslots()],
+                                                double acc[8], double& rate) {
+  using G = TileGeo<TX, TY, TZ>;
+  constexpr int SX = G::SX[D], SY = G::SY[D];
+  constexpr int T_D = (D == 0) ? TX : (D == 1 ? TY : TZ);
+  constexpr int TA = (D == 0) ? TY : TX;           // first other axis extent
+  constexpr int NEXTRA = (D == 0) ? TY * TZ : (D == 1 ? TX * TZ : TX * TY);
+  constexpr int AX = (D == 0) ? 1 : 0;             // first other axis
+  constexpr int BX = (D == 2) ? 1 : 2;             // second other axis
+  const int tid = threadIdx.x;
+  const int lastD = min(T_D, bx.n[D] - org[D]);    // face index after the tile's last valid cell
+  for (int job = tid; job < 256 + NEXTRA; job += 256) {
+    int fl[3];
+    bool ok;
+    if (job < 256) {
+      fl[0] = l[0];
+      fl[1] = l[1];
+      fl[2] = l[2];
+      ok = valid;
+    } else {
+      const int e = job - 256;
+      fl[AX] = e % TA;
+      fl[BX] = e / TA;
+      fl[D] = lastD;
+      ok = (org[AX] + fl[AX] < bx.n[AX]) && (org[BX] + fl[BX] < bx.n[BX]);
+    }
+    if (ok) {
+      double F[8];
+      face_flux<D, RECON, R, SHIFT>(a, bx, Pb, alb, beb, gab, org[0] + fl[0], org[1] + fl[1], org[2] + fl[2], F,
+                                    rate);
+      const int slot = fl[0] + SX * (fl[1] + SY * fl[2]);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) sF[q][slot] = F[q];
+    }
+  }
+  __syncthreads();
+  if (valid) {
+    const int lo = l[0] + SX * (l[1] + SY * l[2]);
+    const int hi = lo + ((D == 0) ? 1 : (D == 1 ? SX : SX * SY));
+    const double idx = bx.inv_dx[D];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc[q] += (sF[q][lo] - sF[q][hi]) * idx;
+  }
+  __syncthreads();
+}
+
+template <int RECON, typename R, bool SHIFT, int TI>
+__global__ __launch_bounds__(256) void k_stage(StageArgs a) {
+  constexpr int TX = TILE_X[TI], TY = TILE_Y[TI], TZ = TILE_Z[TI];
+  using G = TileGeo<TX, TY, TZ>;
+  __shared__ double sF[8][G::maxslots()];
+  const int b = find_box(a.tab.tile_prefix + TI * (a.tab.nbox + 1), a.tab.nbox, blockIdx.x);
+  const KBox& bx = a.tab.box[b];
+  const int t = blockIdx.x - a.tab.tile_prefix[TI * (a.tab.nbox + 1) + b];
+  const int ntx = (bx.n[0] + TX - 1) / TX, nty = (bx.n[1] + TY - 1) / TY;
+  const int org[3] = {(t % ntx) * TX, ((t / ntx) % nty) * TY, (t / (ntx * nty)) * TZ};
+  const int tid = threadIdx.x;
+  const int l[3] = {tid % TX, (tid / TX) % TY, tid / (TX * TY)};
+  const int i = org[0] + l[0], j = org[1] + l[1], k = org[2] + l[2];
+  const bool valid = (i < bx.n[0]) && (j < bx.n[1]) && (k < bx.n[2]);
+  const double* __restrict__ Pb = a.P + bx.cell_off;
+  const double* __restrict__ alb = a.alpha + bx.vert_off;
+  const double* __restrict__ beb = SHIFT ? a.beta + bx.vert_off : nullptr;
+  const double* __restrict__ gab = a.gamma + bx.vert_off;
+  double acc[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) acc[q] = 0.0;
+  double rate = 0.0;
+  direction_phase<0, RECON, R, SHIFT, TX, TY, TZ>(a, bx, Pb, alb, beb, gab, org, l, valid, sF, acc, rate);
+  direction_phase<1, RECON, R, SHIFT, TX, TY, TZ>(a, bx, Pb, alb, beb, gab, org, l, valid, sF, acc, rate);
+  direction_phase<2, RECON, R, SHIFT, TX, TY, TZ>(a, bx, Pb, alb, beb, gab, org, l, valid, sF, acc, rate);
+  if (valid) {
+    const int ng = bx.ng;
+    const int c = ((k + ng) * (bx.NXY / bx.NX) + (j + ng)) * bx.NX + (i + ng);
+    const int vb = ((k + ng) * (bx.VXY / bx.VX) + (j + ng)) * bx.VX + (i + ng);
+    CentreMetric cm;
+    centre_metric<SHIFT, true>(alb, beb, gab, a.vs, vb, bx.VX, bx.VXY, cm);
+    double P[8], S[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) P[q] = Pb[q * a.cs + c];
+    sources<SHIFT>(alb, beb, gab, a.vs, vb, bx.VX, bx.VXY, bx.inv_dx, cm, P, a.ph.gam, S);
+    const int64_t cc = bx.cell_off + c;
+    if (a.mode == 0) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) a.Uout[q * a.cs + cc] = acc[q] + S[q];
+    } else {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const double un = a.Un[q * a.cs + cc];
+        const double us = a.Us[q * a.cs + cc];
+        a.Uout[q * a.cs + cc] = un + a.cstage * ((us - un) + a.dt * (acc[q] + S[q]));
+      }
+    }
+  }
+  if (a.max_rate) block_max_atomic(rate, a.max_rate);
+}
+
+// ---------------------------------------------------------------- cell kernels
+
+__device__ __forceinline__ bool cell_of(const Table& tab, int blk, int tid, int& b, int& c, int& vb) {
+  b = find_box(tab.c2p_prefix, tab.nbox, blk);
+  const KBox& bx = tab.box[b];
+  const int lin = (blk - tab.c2p_prefix[b]) * C2P_BLOCK + tid;
+  const int nxy = bx.n[0] * bx.n[1];
+  if (lin >= nxy * bx.n[2]) return false;
+  const int k = lin / nxy;
+  const int r = lin - k * nxy;
+  const int j = r / bx.n[0];
+  const int i = r - j * bx.n[0];
+  const int ng = bx.ng;
+  c = ((k + ng) * (bx.NXY / bx.NX) + (j + ng)) * bx.NX + (i + ng);
+  vb = ((k + ng) * (bx.VXY / bx.VX) + (j + ng)) * bx.VX + (i + ng);
+  return true;
+}
+
+__global__ __launch_bounds__(C2P_BLOCK) void k_con2prim(CellArgs a) {
+  int b, c, vb;
+  unsigned long long fail = 0;
+  if (cell_of(a.tab, blockIdx.x, threadIdx.x, b, c, vb)) {
+    const KBox& bx = a.tab.box[b];
+    CentreMetric cm;
+    centre_metric<false, false>(nullptr, nullptr, a.gamma + bx.vert_off, a.vs, vb, bx.VX, bx.VXY, cm);
+    const int64_t cc = bx.cell_off + c;
+    double U[8], P[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      U[q] = a.U[q * a.cs + cc];
+      P[q] = a.P[q * a.cs + cc];
+    }
+    const int st = c2p_cell(cm.g, cm.gi, cm.sqrtg, a.ph, U, P);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) a.P[q * a.cs + cc] = P[q];
+    if (st != C2P_OK && st != C2P_FALLBACK) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) a.U[q * a.cs + cc] = U[q];
+    }
+    if (a.ckpt) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) a.ckpt[q * a.cs + cc] = U[q];
+    }
+    if (a.status) a.status[cc] = st;
+    fail = (st >= C2P_NOCONV && st <= C2P_NONFINITE) ? 1ull : 0ull;
+  }
+  if (a.n_fail) {
+    for (int o = 32; o > 0; o >>= 1) fail += __shfl_xor(fail, o, 64);
+    if ((threadIdx.x & 63) == 0 && fail) atomicAdd(a.n_fail, fail);
+  }
+}
+
+__global__ __launch_bounds__(C2P_BLOCK) void k_prim2con(Table tab, const double* __restrict__ P,
+                                                        double* __restrict__ U, const double* __restrict__ gamma,
+                                                        int64_t cs, int64_t vs, double gm1) {
+  int b, c, vb;
+  if (!cell_of(tab, blockIdx.x, threadIdx.x, b, c, vb)) return;
+  const KBox& bx = tab.box[b];
+  CentreMetric cm;
+  centre_metric<false, false>(nullptr, nullptr, gamma + bx.vert_off, vs, vb, bx.VX, bx.VXY, cm);
+  const int64_t cc = bx.cell_off + c;
+  double p[8], u[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) p[q] = P[q * cs + cc];
+  p2c_cell(cm.g, cm.sqrtg, gm1, p, u);
+#pragma unroll
+  for (int q = 0; q < 8; ++q) U[q * cs + cc] = u[q];
+}
+
+// ---------------------------------------------------------------- host side
+
+thread_local std::string g_last_error;
+
+// ---- optional per-launch timing (benchmarks) ----
+struct TimedLaunch {
+  hipEvent_t a, b;
+  int kind;
+};
+bool g_timing = false;
+std::vector<TimedLaunch> g_timed;      // pending pairs
+std::vector<hipEvent_t> g_event_pool;  // reusable events
+double g_time_ms[2] = {0, 0};
+int64_t g_time_n[2] = {0, 0};
+
+hipEvent_t pool_event() {
+  if (!g_event_pool.empty()) {
+    hipEvent_t e = g_event_pool.back();
+    g_event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+void drain_timing() {
+  for (auto& t : g_timed) {
+    float ms = 0.f;
+    if (hipEventSynchronize(t.b) == hipSuccess && hipEventElapsedTime(&ms, t.a, t.b) == hipSuccess) {
+      g_time_ms[t.kind] += ms;
+      g_time_n[t.kind] += 1;
+    }
+    g_event_pool.push_back(t.a);
+    g_event_pool.push_back(t.b);
+  }
+  g_timed.clear();
+}
+
+struct TimeScope {
+  hipEvent_t a = nullptr, b = nullptr;
+  hipStream_t s;
+  int kind;
+  TimeScope(int k, hipStream_t st) : s(st), kind(k) {
+    if (!g_timing) return;
+    if (g_timed.size() > 4096) drain_timing();
+    a = pool_event();
+    b = pool_event();
+    if (a) hipEventRecord(a, s);
+  }
+  ~TimeScope() {
+    if (!a || !b) return;
+    hipEventRecord(b, s);
+    g_timed.push_back({a, b, kind});
+  }
+};
+
+struct Prepared {
+  uint64_t hash;
+  int32_t nbox;
+  int64_t c2p_blocks;
+  int64_t tiles[NTILE];
+};
+std::mutex g_mu;
+std::unordered_map<const void*, Prepared> g_prepared;
+
+uint64_t fnv1a(const void* p, size_t n, uint64_t h = 1469598103934665603ull) {
+  const unsigned char* c = static_cast<const unsigned char*>(p);
+  for (size_t i = 0; i < n; ++i) {
+    h ^= c[i];
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+uint64_t domain_hash(const grmhd_domain* dom) {
+  uint64_t h = fnv1a(&dom->nbox, sizeof(dom->nbox));
+  h = fnv1a(&dom->cell_stride, sizeof(dom->cell_stride), h);
+  h = fnv1a(&dom->vert_stride, sizeof(dom->vert_stride), h);
+  return fnv1a(dom->box, sizeof(grmhd_box) * (size_t)dom->nbox, h);
+}
+
+int fail_hip(hipError_t e, const char* what) {
+  g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+  return GRMHD_EHIP;
+}
+
+int invalid(const char* why) {
+  g_last_error = why;
+  return GRMHD_EINVAL;
+}
+
+size_t table_bytes(int32_t nbox) {
+  return sizeof(TableHeader) + sizeof(KBox) * (size_t)nbox + sizeof(int32_t) * (size_t)(nbox + 1) * (1 + NTILE);
+}
+
+int periodic_map(int m, int n) { return ((m % n) + n) % n; }
+
+int check_box(const grmhd_box& b, int64_t cs, int64_t vs) {
+  for (int d = 0; d < 3; ++d) {
+    if (b.n[d] < 1) return invalid("box with n < 1");
+    if (!(b.dx[d] > 0.0) || !std::isfinite(b.dx[d])) return invalid("box with dx <= 0 or non-finite");
+    if (!std::isfinite(b.x0[d])) return invalid("box with non-finite x0");
+  }
+  for (int q = 0; q < 6; ++q)
+    if (b.bc[q] != GRMHD_BC_PERIODIC && b.bc[q] != GRMHD_BC_OUTFLOW) return invalid("unknown boundary code");
+  for (int d = 0; d < 3; ++d)
+    if ((b.bc[2 * d] == GRMHD_BC_PERIODIC) != (b.bc[2 * d + 1] == GRMHD_BC_PERIODIC))
+      return invalid("periodic boundary on only one side of an axis");
+  if (b.ng < 2 || b.ng > 16) return invalid("ghost layers must be in [2, 16]");
+  const int64_t NX = b.n[0] + 2 * b.ng, NY = b.n[1] + 2 * b.ng, NZ = b.n[2] + 2 * b.ng;
+  const int64_t nc = NX * NY * NZ, nv = (NX + 1) * (NY + 1) * (NZ + 1);
+  if (nv >= (int64_t(1) << 31)) return invalid("box too large for 32-bit indexing");
+  if (b.cell_off < 0 || b.cell_off + nc > cs) return invalid("box cells outside the cell stride");
+  if (b.vert_off < 0 || b.vert_off + nv > vs) return invalid("box vertices outside the vertex stride");
+  return GRMHD_OK;
+}
+
+int check_domain_struct(const grmhd_domain* dom) {
+  if (!dom || !dom->box || dom->nbox < 1 || !dom->table) return invalid("null domain, box list or table");
+  if (dom->cell_stride < 1 || dom->vert_stride < 1) return invalid("bad field strides");
+  for (int b = 0; b < dom->nbox; ++b) {
+    int r = check_box(dom->box[b], dom->cell_stride, dom->vert_stride);
+    if (r) return r;
+  }
+  // boxes must not overlap in the pooled arrays
+  std::vector<std::pair<int64_t, int64_t>> iv;
+  for (int b = 0; b < dom->nbox; ++b) {
+    const grmhd_box& x = dom->box[b];
+    const int64_t nc = int64_t(x.n[0] + 2 * x.ng) * (x.n[1] + 2 * x.ng) * (x.n[2] + 2 * x.ng);
+    iv.push_back({x.cell_off, x.cell_off + nc});
+  }
+  std::sort(iv.begin(), iv.end());
+  for (size_t q = 1; q < iv.size(); ++q)
+    if (iv[q].first < iv[q - 1].second) return invalid("boxes overlap in the cell arrays");
+  return GRMHD_OK;
+}
+
+// Validated, prepared domain: returns the launch totals.
+int check_domain(const grmhd_domain* dom, Prepared& out) {
+  if (!dom || !dom->box || !dom->table) return invalid("null domain, box list or table");
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_prepared.find(dom->table);
+  if (it == g_prepared.end()) return invalid("domain table not prepared (call grmhd_domain_prepare)");
+  if (it->second.nbox != dom->nbox || it->second.hash != domain_hash(dom))
+    return invalid("domain changed since grmhd_domain_prepare");
+  out = it->second;
+  return GRMHD_OK;
+}
+
+int check_params(const grmhd_params* p, const grmhd_domain* dom, KPhys& ph) {
+  if (!p) return invalid("null params");
+  if (p->recon < GRMHD_RECON_MINMOD || p->recon > GRMHD_RECON_WENOZ) return invalid("unknown reconstruction");
+  if (p->precision != GRMHD_FP64 && p->precision != GRMHD_MIXED) return invalid("unknown precision");
+  if (!(p->eos_gamma > 1.0) || !std::isfinite(p->eos_gamma)) return invalid("eos_gamma must be > 1");
+  if (!(p->weno_eps > 0.0) || !(p->wenoz_eps > 0.0) || !std::isfinite(p->weno_eps) || !std::isfinite(p->wenoz_eps))
+    return invalid("WENO epsilons must be positive");
+  if (p->wenoz_p != 1 && p->wenoz_p != 2) return invalid("wenoz_p must be 1 or 2");
+  if (!(p->c2p_tol > 0.0) || p->c2p_maxit < 1 || p->c2p_maxit > 100000) return invalid("bad con2prim tolerance");
+  if (p->tile < -1 || p->tile >= NTILE) return invalid("unknown tile shape");
+  if (!(p->rho_atm > 0.0) || !(p->atm_K > 0.0) || !(p->atm_gamma > 0.0) || !std::isfinite(p->rho_atm) ||
+      !std::isfinite(p->atm_K) || !std::isfinite(p->atm_gamma))
+    return invalid("bad atmosphere parameters");
+  const int need = (p->recon == GRMHD_RECON_MINMOD) ? 2 : 3;
+  if (dom)
+    for (int b = 0; b < dom->nbox; ++b)
+      if (dom->box[b].ng < need) return invalid("not enough ghost layers for the reconstruction");
+  ph.gam = p->eos_gamma;
+  ph.gm1 = p->eos_gamma - 1.0;
+  ph.gf = p->eos_gamma / (p->eos_gamma - 1.0);
+  ph.weno_eps = p->weno_eps;
+  ph.wenoz_eps = p->wenoz_eps;
+  ph.wenoz_p = p->wenoz_p;
+  ph.c2p_tol = p->c2p_tol;
+  ph.c2p_maxit = p->c2p_maxit;
+  ph.rho_atm = p->rho_atm;
+  ph.p_atm = p->atm_K * std::pow(p->rho_atm, p->atm_gamma);
+  ph.eps_atm = ph.p_atm / ((p->eos_gamma - 1.0) * p->rho_atm);
+  return GRMHD_OK;
+}
+
+Table make_table(const grmhd_domain* dom) {
+  Table t;
+  const char* base = static_cast<const char*>(dom->table);
+  t.box = reinterpret_cast<const KBox*>(base + sizeof(TableHeader));
+  t.c2p_prefix = reinterpret_cast<const int32_t*>(base + sizeof(TableHeader) + sizeof(KBox) * (size_t)dom->nbox);
+  t.tile_prefix = t.c2p_prefix + (dom->nbox + 1);
+  t.nbox = dom->nbox;
+  return t;
+}
+
+int pick_tile(const grmhd_domain* dom, const grmhd_params* par) {
+  if (par->tile >= 0) return par->tile;
+  (void)dom;
+  return 0;
+}
+
+template <int RECON, typename R, bool SHIFT, int TI>
+hipError_t launch_stage_t(const StageArgs& a, int64_t blocks, hipStream_t s) {
+  hipLaunchKernelGGL((k_stage<RECON, R, SHIFT, TI>), dim3((unsigned)blocks), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+template <int RECON, typename R, bool SHIFT>
+hipError_t launch_stage_r(const StageArgs& a, int64_t blocks, hipStream_t s) {
+  switch (a.tile) {
+    case 0: return launch_stage_t<RECON, R, SHIFT, 0>(a, blocks, s);
+    case 1: return launch_stage_t<RECON, R, SHIFT, 1>(a, blocks, s);
+    default: return launch_stage_t<RECON, R, SHIFT, 2>(a, blocks, s);
+  }
+}
+
+template <int RECON>
+hipError_t launch_stage_p(const StageArgs& a, int precision, int64_t blocks, hipStream_t s) {
+  const bool sh = a.beta != nullptr;
+  if (precision == GRMHD_MIXED)
+    return sh ? launch_stage_r<RECON, float, true>(a, blocks, s) : launch_stage_r<RECON, float, false>(a, blocks, s);
+  return sh ? launch_stage_r<RECON, double, true>(a, blocks, s) : launch_stage_r<RECON, double, false>(a, blocks, s);
+}
+
+hipError_t launch_stage(const StageArgs& a, int recon, int precision, int64_t blocks, hipStream_t s) {
+  if (blocks <= 0) return hipSuccess;
+  TimeScope ts(0, s);
+  switch (recon) {
+    case GRMHD_RECON_MINMOD: return launch_stage_p<GRMHD_RECON_MINMOD>(a, precision, blocks, s);
+    case GRMHD_RECON_WENO5: return launch_stage_p<GRMHD_RECON_WENO5>(a, precision, blocks, s);
+    default: return launch_stage_p<GRMHD_RECON_WENOZ>(a, precision, blocks, s);
+  }
+}
+
+int check_metric(const grmhd_metric* m, bool need_alpha) {
+  if (!m || !m->gamma || (need_alpha && !m->alpha)) return invalid("null metric field");
+  return GRMHD_OK;
+}
+
+hipError_t launch_c2p(const grmhd_domain* dom, const Prepared& pr, const KPhys& ph, const grmhd_metric* met, double* U,
+                      double* P, double* ckpt, int32_t* status, int64_t* n_fail, hipStream_t s) {
+  CellArgs a;
+  a.tab = make_table(dom);
+  a.U = U;
+  a.P = P;
+  a.ckpt = ckpt;
+  a.status = status;
+  a.n_fail = reinterpret_cast<unsigned long long*>(n_fail);
+  a.gamma = met->gamma;
+  a.cs = dom->cell_stride;
+  a.vs = dom->vert_stride;
+  a.ph = ph;
+  TimeScope ts(1, s);
+  hipLaunchKernelGGL(k_con2prim, dim3((unsigned)pr.c2p_blocks), dim3(C2P_BLOCK), 0, s, a);
+  return hipGetLastError();
+}
+
+StageArgs stage_args(const grmhd_domain* dom, const grmhd_params* par, const KPhys& ph, const grmhd_metric* met,
+                     const double* P) {
+  StageArgs a;
+  a.tab = make_table(dom);
+  a.tile = pick_tile(dom, par);
+  a.P = P;
+  a.Us = a.Un = nullptr;
+  a.Uout = nullptr;
+  a.alpha = met->alpha;
+  a.beta = met->beta;
+  a.gamma = met->gamma;
+  a.cs = dom->cell_stride;
+  a.vs = dom->vert_stride;
+  a.cstage = 1.0;
+  a.dt = 0.0;
+  a.mode = 0;
+  a.ph = ph;
+  a.max_rate = nullptr;
+  return a;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t grmhd_domain_table_bytes(int32_t nbox) { return nbox < 1 ? 0 : table_bytes(nbox); }
+
+int grmhd_domain_prepare(const grmhd_domain* dom, void* stream) {
+  int r = check_domain_struct(dom);
+  if (r) return r;
+  const int nb = dom->nbox;
+  std::vector<char> buf(table_bytes(nb), 0);
+  TableHeader* h = reinterpret_cast<TableHeader*>(buf.data());
+  KBox* kb = reinterpret_cast<KBox*>(buf.data() + sizeof(TableHeader));
+  int32_t* c2p = reinterpret_cast<int32_t*>(buf.data() + sizeof(TableHeader) + sizeof(KBox) * nb);
+  int32_t* tp = c2p + (nb + 1);
+  Prepared pr;
+  int64_t acc_c2p = 0, acc_t[NTILE] = {0, 0, 0};
+  for (int b = 0; b < nb; ++b) {
+    const grmhd_box& x = dom->box[b];
+    KBox& k = kb[b];
+    std::memset(&k, 0, sizeof(k));
+    for (int d = 0; d < 3; ++d) k.n[d] = x.n[d];
+    k.ng = x.ng;
+    k.NX = x.n[0] + 2 * x.ng;
+    k.NXY = k.NX * (x.n[1] + 2 * x.ng);
+    k.VX = k.NX + 1;
+    k.VXY = k.VX * (x.n[1] + 2 * x.ng + 1);
+    k.cell_off = x.cell_off;
+    k.vert_off = x.vert_off;
+    for (int d = 0; d < 3; ++d) {
+      k.inv_dx[d] = 1.0 / x.dx[d];
+      const bool per = x.bc[2 * d] == GRMHD_BC_PERIODIC;
+      for (int o = 0; o < 3; ++o) {
+        const int mlo = o - 3, mhi = x.n[d] + o;
+        k.mlo[d][o] = per ? periodic_map(mlo, x.n[d]) : 0;
+        k.mhi[d][o] = per ? periodic_map(mhi, x.n[d]) : x.n[d] - 1;
+      }
+    }
+    c2p[b] = (int32_t)acc_c2p;
+    const int64_t nint = int64_t(x.n[0]) * x.n[1] * x.n[2];
+    acc_c2p += (nint + C2P_BLOCK - 1) / C2P_BLOCK;
+    for (int t = 0; t < NTILE; ++t) {
+      tp[t * (nb + 1) + b] = (int32_t)acc_t[t];
+      acc_t[t] += int64_t((x.n[0] + TILE_X[t] - 1) / TILE_X[t]) * ((x.n[1] + TILE_Y[t] - 1) / TILE_Y[t]) *
+                  ((x.n[2] + TILE_Z[t] - 1) / TILE_Z[t]);
+    }
+  }
+  if (acc_c2p >= (int64_t(1) << 31)) return invalid("too many cells");
+  c2p[nb] = (int32_t)acc_c2p;
+  for (int t = 0; t < NTILE; ++t) {
+    if (acc_t[t] >= (int64_t(1) << 31)) return invalid("too many tiles");
+    tp[t * (nb + 1) + nb] = (int32_t)acc_t[t];
+  }
+  h->magic = TABLE_MAGIC;
+  h->hash = domain_hash(dom);
+  h->nbox = nb;
+  h->c2p_blocks = acc_c2p;
+  for (int t = 0; t < NTILE; ++t) h->tiles[t] = acc_t[t];
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = hipMemcpyAsync(dom->table, buf.data(), buf.size(), hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return fail_hip(e, "hipMemcpyAsync(table)");
+  e = hipStreamSynchronize(s);  // the host staging buffer dies with this call
+  if (e != hipSuccess) return fail_hip(e, "hipStreamSynchronize");
+  pr.hash = h->hash;
+  pr.nbox = nb;
+  pr.c2p_blocks = acc_c2p;
+  for (int t = 0; t < NTILE; ++t) pr.tiles[t] = acc_t[t];
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_prepared[dom->table] = pr;
+  return GRMHD_OK;
+}
+
+int grmhd_prim2con(const grmhd_domain* dom, const grmhd_params* par, const grmhd_metric* met, const double* P,
+                   double* U, void* stream) {
+  Prepared pr;
+  KPhys ph;
+  int r;
+  if ((r = check_domain(dom, pr)) || (r = check_params(par, nullptr, ph)) || (r = check_metric(met, false))) return r;
+  if (!P || !U) return invalid("null P or U");
+  hipLaunchKernelGGL(k_prim2con, dim3((unsigned)pr.c2p_blocks), dim3(C2P_BLOCK), 0, static_cast<hipStream_t>(stream),
+                     make_table(dom), P, U, met->gamma, dom->cell_stride, dom->vert_stride, ph.gm1);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? GRMHD_OK : fail_hip(e, "k_prim2con");
+}
+
+int grmhd_con2prim(const grmhd_domain* dom, const grmhd_params* par, const grmhd_metric* met, double* U, double* P,
+                   int32_t* status, int64_t* n_fail, void* stream) {
+  Prepared pr;
+  KPhys ph;
+  int r;
+  if ((r = check_domain(dom, pr)) || (r = check_params(par, nullptr, ph)) || (r = check_metric(met, false))) return r;
+  if (!P || !U) return invalid("null P or U");
+  hipError_t e = launch_c2p(dom, pr, ph, met, U, P, nullptr, status, n_fail, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? GRMHD_OK : fail_hip(e, "k_con2prim");
+}
+
+int grmhd_rhs(const grmhd_domain* dom, const grmhd_params* par, const grmhd_metric* met, double* U, double* P,
+              double* dUdt, double* max_rate, int64_t* n_fail, void* stream) {
+  Prepared pr;
+  KPhys ph;
+  int r;
+  if ((r = check_domain(dom, pr)) || (r = check_params(par, dom, ph)) || (r = check_metric(met, true))) return r;
+  if (!P || !U || !dUdt) return invalid("null P, U or dUdt");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = launch_c2p(dom, pr, ph, met, U, P, nullptr, nullptr, n_fail, s);
+  if (e != hipSuccess) return fail_hip(e, "k_con2prim");
+  StageArgs a = stage_args(dom, par, ph, met, P);
+  a.Uout = dUdt;
+  a.mode = 0;
+  a.max_rate = max_rate;
+  e = launch_stage(a, par->recon, par->precision, pr.tiles[a.tile], s);
+  return e == hipSuccess ? GRMHD_OK : fail_hip(e, "k_stage");
+}
+
+size_t grmhd_workspace_bytes(const grmhd_domain* dom, const grmhd_params* par, int32_t scheme, int32_t for_adjoint) {
+  (void)par;
+  (void)scheme;
+  if (!dom || dom->cell_stride < 1) return 0;
+  const size_t field = sizeof(double) * 8 * (size_t)dom->cell_stride;
+  return for_adjoint ? 4 * field : field;
+}
+
+int grmhd_rk_step(const grmhd_domain* dom, const grmhd_params* par, const grmhd_metric* met, double* U, double* P,
+                  double dt, int32_t scheme, double* stage_ckpt, double* max_rate, int64_t* n_fail, void* ws,
+                  size_t ws_bytes, void* stream) {
+  Prepared pr;
+  KPhys ph;
+  int r;
+  if ((r = check_domain(dom, pr)) || (r = check_params(par, dom, ph)) || (r = check_metric(met, true))) return r;
+  if (!P || !U) return invalid("null P or U");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return invalid("dt must be positive and finite");
+  if (scheme != GRMHD_SSPRK3 && scheme != GRMHD_SSPRK2) return invalid("unknown time integrator");
+  if (!ws) return invalid("null workspace");
+  if (ws_bytes < grmhd_workspace_bytes(dom, par, scheme, 0)) {
+    g_last_error = "workspace too small";
+    return GRMHD_EWORKSPACE;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  static const double c3[3] = {1.0, 0.25, 2.0 / 3.0};
+  static const double c2[2] = {1.0, 0.5};
+  const double* cst = scheme == GRMHD_SSPRK2 ? c2 : c3;
+  const int nst = scheme == GRMHD_SSPRK2 ? 2 : 3;
+  double* W1 = static_cast<double*>(ws);
+  const size_t fsz = 8 * (size_t)dom->cell_stride;
+  hipError_t e = launch_c2p(dom, pr, ph, met, U, P, stage_ckpt, nullptr, n_fail, s);
+  if (e != hipSuccess) return fail_hip(e, "k_con2prim");
+  StageArgs a = stage_args(dom, par, ph, met, P);
+  a.mode = 1;
+  a.dt = dt;
+  a.max_rate = max_rate;
+  a.Un = U;
+  for (int st = 0; st < nst; ++st) {
+    a.Us = (st == 0) ? U : W1;
+    a.Uout = (st == nst - 1) ? U : W1;
+    a.cstage = cst[st];
+    e = launch_stage(a, par->recon, par->precision, pr.tiles[a.tile], s);
+    if (e != hipSuccess) return fail_hip(e, "k_stage");
+    double* ck = (stage_ckpt && st + 1 < nst) ? stage_ckpt + (st + 1) * fsz : nullptr;
+    e = launch_c2p(dom, pr, ph, met, a.Uout, P, ck, nullptr, n_fail, s);
+    if (e != hipSuccess) return fail_hip(e, "k_con2prim");
+  }
+  return GRMHD_OK;
+}
+
+int grmhd_timing_enable(int32_t on) {
+  drain_timing();
+  g_timing = on != 0;
+  g_time_ms[0] = g_time_ms[1] = 0.0;
+  g_time_n[0] = g_time_n[1] = 0;
+  return GRMHD_OK;
+}
+
+int grmhd_timing_read(double* ms, int64_t* launches) {
+  if (!ms || !launches) return invalid("null output");
+  drain_timing();
+  for (int k = 0; k < 2; ++k) {
+    ms[k] = g_time_ms[k];
+    launches[k] = g_time_n[k];
+  }
+  return GRMHD_OK;
+}
+
+const char* grmhd_strerror(int code) {
+  switch (code) {
+    case GRMHD_OK: return "success";
+    case GRMHD_EINVAL: return "invalid argument";
+    case GRMHD_EHIP: return "HIP runtime error";
+    case GRMHD_EWORKSPACE: return "workspace too small";
+    default: return "unknown error";
+  }
+}
+
+const char* grmhd_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

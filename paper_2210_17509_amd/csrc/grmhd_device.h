@@ -1,0 +1,712 @@
+// Device-side building blocks of the gfx950 GRMHD hot path (GRaM-X,
+// arXiv:2210.17509): pointwise prim->cons, fluxes and wave speeds,
+// reconstruction, HLLE, static-metric source terms and con2prim.
+//
+// R is the arithmetic type of reconstruction and HLLE (double, or float in the
+// mixed-precision mode); everything else is double.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gk {
+
+// ---------------------------------------------------------------- launch tables
+
+constexpr int NTILE = 3;  // compiled stage-kernel tile shapes
+constexpr int C2P_BLOCK = 256;
+
+// Per-box data the kernels read (derived on the host from grmhd_box).
+struct KBox {
+  int32_t n[3];
+  int32_t ng;
+  int32_t NX, NXY;  // storage cell strides (x, xy) including ghosts
+  int32_t VX, VXY;  // vertex strides
+  int64_t cell_off, vert_off;
+  double inv_dx[3];
+  int32_t mlo[3][3];  // interior index read for ghost coordinates -3, -2, -1
+  int32_t mhi[3][3];  // interior index read for coordinates n, n+1, n+2
+  int32_t pad[2];
+};
+static_assert(sizeof(KBox) % 8 == 0, "KBox alignment");
+
+struct TableHeader {
+  uint64_t magic;
+  uint64_t hash;
+  int32_t nbox;
+  int32_t pad;
+  int64_t c2p_blocks;
+  int64_t tiles[NTILE];
+};
+
+// Device table: header | KBox[nbox] | int32 c2p_prefix[nbox+1] | int32 tile_prefix[NTILE][nbox+1]
+struct Table {
+  const KBox* box;
+  const int32_t* c2p_prefix;
+  const int32_t* tile_prefix;  // [NTILE][nbox+1]
+  int32_t nbox;
+};
+
+__device__ __forceinline__ int find_box(const int32_t* prefix, int nbox, int blk) {
+  int lo = 0, hi = nbox;  // prefix[lo] <= blk < prefix[hi]
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (prefix[mid] <= blk) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// ---------------------------------------------------------------- physics constants
+
+struct KPhys {
+  double gam, gm1, gf;      // Gamma, Gamma - 1, Gamma / (Gamma - 1)
+  double weno_eps, wenoz_eps;
+  double c2p_tol;
+  double rho_atm, p_atm, eps_atm;
+  int32_t c2p_maxit, wenoz_p;
+};
+
+// ---------------------------------------------------------------- small helpers
+
+template <typename R> __device__ __forceinline__ R rsq(R x) { return x * x; }
+__device__ __forceinline__ double sqrt_r(double x) { return sqrt(x); }
+__device__ __forceinline__ float sqrt_r(float x) { return sqrtf(x); }
+template <typename R> __device__ __forceinline__ R rmax(R a, R b) { return a < b ? b : a; }
+template <typename R> __device__ __forceinline__ R rmin(R a, R b) { return b < a ? b : a; }
+template <typename R> __device__ __forceinline__ R rabs(R a) { return a < R(0) ? -a : a; }
+
+// symmetric 3x3 storage: xx xy xz yy yz zz
+__device__ __forceinline__ constexpr int sidx(int i, int j) {
+  return (i == 0) ? j : (i == 1 ? (j == 0 ? 1 : j + 2) : (j == 0 ? 2 : (j == 1 ? 4 : 5)));
+}
+
+// ---------------------------------------------------------------- face metric
+
+template <typename R> struct FaceMetric {
+  R alpha, beta[3], g[6], sqrtg, gdd;
+};
+
+// Mean of the four vertices of the low face (direction D) of the cell whose
+// lower corner is vertex vb: the metric is interpolated linearly from the
+// vertices to the face centre (Sec. II C).
+template <int D, bool SHIFT, typename R>
+__device__ __forceinline__ void face_metric(const double* __restrict__ alpha, const double* __restrict__ beta,
+                                            const double* __restrict__ gamma, int64_t vs, int vb, int sa, int sb,
+                                            FaceMetric<R>& m) {
+  const int v0 = vb, v1 = vb + sa, v2 = vb + sb, v3 = vb + sa + sb;
+  auto avg = [&](const double* __restrict__ f) -> double { return 0.25 * ((f[v0] + f[v1]) + (f[v2] + f[v3])); };
+  double g[6];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) g[q] = avg(gamma + q * vs);
+  m.alpha = (R)avg(alpha);
+#pragma unroll
+  for (int q = 0; q < 3; ++q) m.beta[q] = SHIFT ? (R)avg(beta + q * vs) : R(0);
+  // cofactors: det and the one inverse component gamma^{DD}
+  const double cxx = g[3] * g[5] - g[4] * g[4];
+  const double cxy = g[2] * g[4] - g[1] * g[5];
+  const double cxz = g[1] * g[4] - g[2] * g[3];
+  const double det = g[0] * cxx + g[1] * cxy + g[2] * cxz;
+  double cdd;
+  if (D == 0) cdd = cxx;
+  else if (D == 1) cdd = g[0] * g[5] - g[2] * g[2];
+  else cdd = g[0] * g[3] - g[1] * g[1];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) m.g[q] = (R)g[q];
+  m.sqrtg = (R)sqrt(det);
+  m.gdd = (R)(cdd / det);
+}
+
+// ---------------------------------------------------------------- one side of a face
+
+// Derived quantities of a primitive state at a face, Eqs. (p2c1)-(p2c4):
+// W, v_i, B_i, alpha b^0 = W B.v, b^2 = (B^2 + (alpha b^0)^2) / W^2, Gamma law.
+template <typename R> struct SideState {
+  R vlow[3], Blow[3];
+  R v2, iW, W, B2, ab0, b2, p, rhoh;
+};
+
+template <typename R>
+__device__ __forceinline__ void side_v2(const FaceMetric<R>& m, const R* P, SideState<R>& s) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+    s.vlow[i] = m.g[sidx(i, 0)] * P[1] + m.g[sidx(i, 1)] * P[2] + m.g[sidx(i, 2)] * P[3];
+  s.v2 = s.vlow[0] * P[1] + s.vlow[1] * P[2] + s.vlow[2] * P[3];
+}
+
+template <typename R> __device__ __forceinline__ bool side_ok(const R* P, R v2) {
+  bool fin = true;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) fin = fin && (P[q] - P[q] == R(0));  // false for inf and NaN
+  return fin && (P[0] > R(0)) && (P[4] > R(0)) && (v2 < R(1));
+}
+
+template <typename R>
+__device__ __forceinline__ void side_rest(const FaceMetric<R>& m, const R* P, R gm1, SideState<R>& s) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+    s.Blow[i] = m.g[sidx(i, 0)] * P[5] + m.g[sidx(i, 1)] * P[6] + m.g[sidx(i, 2)] * P[7];
+  s.iW = sqrt_r(R(1) - s.v2);
+  s.W = R(1) / s.iW;
+  s.B2 = s.Blow[0] * P[5] + s.Blow[1] * P[6] + s.Blow[2] * P[7];
+  const R Bv = s.Blow[0] * P[1] + s.Blow[1] * P[2] + s.Blow[2] * P[3];
+  s.ab0 = s.W * Bv;
+  s.b2 = (s.B2 + s.ab0 * s.ab0) * (s.iW * s.iW);
+  s.p = gm1 * P[0] * P[4];
+  s.rhoh = P[0] * (R(1) + P[4]) + s.p;
+}
+
+// Bounds of the characteristic speeds in direction D: the 3+1 hydrodynamic
+// eigenvalues with the sound speed replaced by the fast magnetosonic bound
+// c_f^2 = c_s^2 + c_a^2 - c_s^2 c_a^2.
+template <int D, typename R>
+__device__ __forceinline__ void side_speeds(const FaceMetric<R>& m, const R* P, const SideState<R>& s, R gam, R& lp,
+                                            R& lm) {
+  const R cs2 = gam * s.p / s.rhoh;
+  const R ca2 = s.b2 / (s.rhoh + s.b2);
+  const R cf2 = cs2 + ca2 - cs2 * ca2;
+  const R vd = P[1 + D];
+  const R den = R(1) - s.v2 * cf2;
+  const R disc = (R(1) - s.v2) * (m.gdd * den - vd * vd * (R(1) - cf2));
+  const R root = sqrt_r(cf2 * rmax(disc, R(0)));
+  const R base = vd * (R(1) - cf2);
+  const R ad = m.alpha / den;
+  lp = ad * (base + root) - m.beta[D];
+  lm = ad * (base - root) - m.beta[D];
+}
+
+// Conserved variables and the direction-D flux, Eqs. (p2c1)-(p2c4) and
+// (definition-of-flux) with v~ = v - beta / alpha.
+template <int D, typename R>
+__device__ __forceinline__ void side_cons_flux(const FaceMetric<R>& m, const R* P, const SideState<R>& s, R U[8],
+                                               R F[8]) {
+  const R sg = m.sqrtg;
+  const R W2 = s.W * s.W;
+  const R rhohs = s.rhoh + s.b2;
+  const R Ps = s.p + R(0.5) * s.b2;
+  R blow[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) blow[i] = s.Blow[i] * s.iW + s.ab0 * s.vlow[i];
+  U[0] = sg * P[0] * s.W;
+#pragma unroll
+  for (int j = 0; j < 3; ++j) U[1 + j] = sg * (rhohs * W2 * s.vlow[j] - s.ab0 * blow[j]);
+  U[4] = sg * (rhohs * W2 - Ps - s.ab0 * s.ab0) - U[0];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) U[5 + k] = sg * P[5 + k];
+  const R a = m.alpha;
+  const R ia = R(1) / a;
+  R vt[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) vt[i] = P[1 + i] - m.beta[i] * ia;
+  const R BnW = U[5 + D] * s.iW;
+  F[0] = a * (U[0] * vt[D]);
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    R t = U[1 + j] * vt[D] - blow[j] * BnW;
+    if (j == D) t = t + sg * Ps;
+    F[1 + j] = a * t;
+  }
+  F[4] = a * (U[4] * vt[D] + sg * Ps * P[1 + D] - s.ab0 * BnW);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) F[5 + k] = (k == D) ? R(0) : a * (U[5 + k] * vt[D] - U[5 + D] * vt[k]);
+}
+
+// ---------------------------------------------------------------- reconstruction
+
+// TVD minmod [Toro]: slope of the centre cell, 0 at extrema.
+template <typename R> __device__ __forceinline__ R minmod(R a, R b) {
+  return (a * b <= R(0)) ? R(0) : (rabs(a) < rabs(b) ? a : b);
+}
+
+// WENO5 value at the right face of the centre cell c of (a, b, c, d, e)
+// [Shu 98]: Jiang-Shu weights d_k / (eps + beta_k)^2 (ZW = false) or Borges
+// WENO-Z weights d_k (1 + (|beta_0 - beta_2| / (beta_k + eps))^p) (ZW = true).
+// The normalisation is folded into a single division.
+template <bool ZW, typename R>
+__device__ __forceinline__ R weno5(R a, R b, R c, R d, R e, R eps, int zp) {
+  const R q0 = R(2) * a - R(7) * b + R(11) * c;  // x6
+  const R q1 = -b + R(5) * c + R(2) * d;
+  const R q2 = R(2) * c + R(5) * d - e;
+  const R b0 = R(13.0 / 12.0) * rsq(a - R(2) * b + c) + R(0.25) * rsq(a - R(4) * b + R(3) * c);
+  const R b1 = R(13.0 / 12.0) * rsq(b - R(2) * c + d) + R(0.25) * rsq(b - d);
+  const R b2 = R(13.0 / 12.0) * rsq(c - R(2) * d + e) + R(0.25) * rsq(R(3) * c - R(4) * d + e);
+  R w0, w1, w2;
+  if (!ZW) {
+    const R t0 = rsq(eps + b0), t1 = rsq(eps + b1), t2 = rsq(eps + b2);
+    w0 = R(0.1) * (t1 * t2);
+    w1 = R(0.6) * (t0 * t2);
+    w2 = R(0.3) * (t0 * t1);
+  } else {
+    const R tau = rabs(b0 - b2);
+    const R e0 = b0 + eps, e1 = b1 + eps, e2 = b2 + eps;
+    if (sizeof(R) == 8) {
+      if (zp == 2) {
+        const R s0 = e0 * e0, s1 = e1 * e1, s2 = e2 * e2, t2 = tau * tau;
+        w0 = R(0.1) * (s0 + t2) * (s1 * s2);
+        w1 = R(0.6) * (s1 + t2) * (s0 * s2);
+        w2 = R(0.3) * (s2 + t2) * (s0 * s1);
+      } else {
+        w0 = R(0.1) * (e0 + tau) * (e1 * e2);
+        w1 = R(0.6) * (e1 + tau) * (e0 * e2);
+        w2 = R(0.3) * (e2 + tau) * (e0 * e1);
+      }
+    } else {  // FP32: the products of tiny eps could underflow, divide per weight
+      R r0 = tau / e0, r1 = tau / e1, r2 = tau / e2;
+      if (zp == 2) { r0 *= r0; r1 *= r1; r2 *= r2; }
+      w0 = R(0.1) * (R(1) + r0);
+      w1 = R(0.6) * (R(1) + r1);
+      w2 = R(0.3) * (R(1) + r2);
+    }
+  }
+  return (w0 * q0 + w1 * q1 + w2 * q2) / (R(6) * (w0 + w1 + w2));
+}
+
+// ---------------------------------------------------------------- HLLE
+
+// F* = (xi+ F_L - xi- F_R + xi+ xi- (U_R - U_L)) / (xi+ - xi-), xi+ = max(0, lambda+),
+// xi- = min(0, lambda-) over both sides [Harten-Lax-van Leer, Einfeldt].
+template <int D, typename R>
+__device__ __forceinline__ void hlle(const FaceMetric<R>& m, const R* PL, const SideState<R>& sL, const R* PR,
+                                     const SideState<R>& sR, R gam, R Fs[8], R& xip, R& xim) {
+  R lpL, lmL, lpR, lmR;
+  side_speeds<D>(m, PL, sL, gam, lpL, lmL);
+  side_speeds<D>(m, PR, sR, gam, lpR, lmR);
+  xip = rmax(R(0), rmax(lpL, lpR));
+  xim = rmin(R(0), rmin(lmL, lmR));
+  const R den = xip - xim;
+  R UL[8], FL[8], UR[8], FR[8];
+  side_cons_flux<D>(m, PL, sL, UL, FL);
+  side_cons_flux<D>(m, PR, sR, UR, FR);
+  if (den > R(0)) {
+    const R id = R(1) / den;
+    const R xx = xip * xim;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) Fs[q] = (xip * FL[q] - xim * FR[q] + xx * (UR[q] - UL[q])) * id;
+  } else {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) Fs[q] = R(0.5) * (FL[q] + FR[q]);
+  }
+}
+
+// ---------------------------------------------------------------- centre metric and sources
+
+struct CentreMetric {
+  double alpha, beta[3], g[6], gi[6], sqrtg;
+};
+
+// Cell-centre metric: mean of the cell's 8 vertices; inverse and sqrt(gamma)
+// from the averaged gamma_ij.
+template <bool SHIFT, bool NEED_ALPHA>
+__device__ __forceinline__ void centre_metric(const double* __restrict__ alpha, const double* __restrict__ beta,
+                                              const double* __restrict__ gamma, int64_t vs, int vb, int VX, int VXY,
+                                              CentreMetric& m) {
+  const int o[8] = {0, 1, VX, VX + 1, VXY, VXY + 1, VXY + VX, VXY + VX + 1};
+  auto avg = [&](const double* __restrict__ f) -> double {
+    return 0.125 * (((f[vb + o[0]] + f[vb + o[1]]) + (f[vb + o[2]] + f[vb + o[3]])) +
+                    ((f[vb + o[4]] + f[vb + o[5]]) + (f[vb + o[6]] + f[vb + o[7]])));
+  };
+#pragma unroll
+  for (int q = 0; q < 6; ++q) m.g[q] = avg(gamma + q * vs);
+  m.alpha = NEED_ALPHA ? avg(alpha) : 1.0;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) m.beta[q] = SHIFT ? avg(beta + q * vs) : 0.0;
+  const double* g = m.g;
+  const double cxx = g[3] * g[5] - g[4] * g[4];
+  const double cxy = g[2] * g[4] - g[1] * g[5];
+  const double cxz = g[1] * g[4] - g[2] * g[3];
+  const double cyy = g[0] * g[5] - g[2] * g[2];
+  const double cyz = g[1] * g[2] - g[0] * g[4];
+  const double czz = g[0] * g[3] - g[1] * g[1];
+  const double det = g[0] * cxx + g[1] * cxy + g[2] * cxz;
+  const double id = 1.0 / det;
+  m.gi[0] = cxx * id; m.gi[1] = cxy * id; m.gi[2] = cxz * id;
+  m.gi[3] = cyy * id; m.gi[4] = cyz * id; m.gi[5] = czz * id;
+  m.sqrtg = sqrt(det);
+}
+
+// d_e f at the cell centre: mean over the 4 edges along e of the vertex
+// difference, times 1/dx_e (second order).
+__device__ __forceinline__ double edge_deriv(const double* __restrict__ f, int vb, int se, int sa, int sb, double idx) {
+  const double s0 = f[vb + se] - f[vb];
+  const double s1 = f[vb + sa + se] - f[vb + sa];
+  const double s2 = f[vb + sb + se] - f[vb + sb];
+  const double s3 = f[vb + sa + sb + se] - f[vb + sa + sb];
+  return 0.25 * ((s0 + s1) + (s2 + s3)) * idx;
+}
+
+// Static-metric source terms of Eq. (definition-of-source) in 3+1 form:
+//   S_Sj  = alpha sqrt(g) [T^00 (beta^i beta^k d_j g_ik / 2 - alpha d_j alpha)
+//           + T^0i beta^k d_j g_ik + T^0_i d_j beta^i + T^ik d_j g_ik / 2]
+//   S_tau = alpha sqrt(g) [T^00 (beta^i beta^j K_ij - beta^i d_i alpha)
+//           + T^0i (2 beta^j K_ij - d_i alpha) + T^ij K_ij]
+// with K_ij = (gamma_jk d_i beta^k + gamma_ik d_j beta^k + beta^k d_k gamma_ij) / (2 alpha)
+// for a time-independent slice; S_D = S_B = 0.
+template <bool SHIFT>
+__device__ __forceinline__ void sources(const double* __restrict__ alpha, const double* __restrict__ beta,
+                                        const double* __restrict__ gamma, int64_t vs, int vb, int VX, int VXY,
+                                        const double* inv_dx, const CentreMetric& m, const double* P, double gam,
+                                        double S[8]) {
+  const int st[3] = {1, VX, VXY};
+  double da[3], dg[3][6], db[3][3];
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    const int se = st[e], sa = st[(e + 1) % 3], sb = st[(e + 2) % 3];
+    da[e] = edge_deriv(alpha, vb, se, sa, sb, inv_dx[e]);
+#pragma unroll
+    for (int q = 0; q < 6; ++q) dg[e][q] = edge_deriv(gamma + q * vs, vb, se, sa, sb, inv_dx[e]);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) db[e][q] = SHIFT ? edge_deriv(beta + q * vs, vb, se, sa, sb, inv_dx[e]) : 0.0;
+  }
+  // 4-velocity, magnetic 4-vector and T^{mu nu} (Eq. (mhd-stress-energy-tensor))
+  double vlow[3], Blow[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    vlow[i] = m.g[sidx(i, 0)] * P[1] + m.g[sidx(i, 1)] * P[2] + m.g[sidx(i, 2)] * P[3];
+    Blow[i] = m.g[sidx(i, 0)] * P[5] + m.g[sidx(i, 1)] * P[6] + m.g[sidx(i, 2)] * P[7];
+  }
+  const double v2 = vlow[0] * P[1] + vlow[1] * P[2] + vlow[2] * P[3];
+  const double iW = sqrt(1.0 - v2);
+  const double W = 1.0 / iW;
+  const double B2 = Blow[0] * P[5] + Blow[1] * P[6] + Blow[2] * P[7];
+  const double Bv = Blow[0] * P[1] + Blow[1] * P[2] + Blow[2] * P[3];
+  const double ia = 1.0 / m.alpha;
+  const double b0 = W * Bv * ia;
+  const double b2 = B2 * (iW * iW) + Bv * Bv;
+  const double p = (gam - 1.0) * P[0] * P[4];
+  const double rhohs = P[0] * (1.0 + P[4]) + p + b2;
+  const double Ps = p + 0.5 * b2;
+  const double u0 = W * ia;
+  double u[3], b[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    u[i] = W * (P[1 + i] - m.beta[i] * ia);
+    b[i] = (P[5 + i] + m.alpha * b0 * u[i]) * iW;
+  }
+  const double ia2 = ia * ia;
+  const double T00 = rhohs * u0 * u0 - Ps * ia2 - b0 * b0;
+  double T0[3], Tij[6];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) T0[i] = rhohs * u0 * u[i] + Ps * m.beta[i] * ia2 - b0 * b[i];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = i; j < 3; ++j)
+      Tij[sidx(i, j)] = rhohs * u[i] * u[j] + Ps * (m.gi[sidx(i, j)] - m.beta[i] * m.beta[j] * ia2) - b[i] * b[j];
+  const double as = m.alpha * m.sqrtg;
+  S[0] = 0.0;
+  S[5] = S[6] = S[7] = 0.0;
+  if (!SHIFT) {
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      double tdg = 0.0;
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) tdg += Tij[sidx(i, k)] * dg[j][sidx(i, k)];
+      S[1 + j] = as * (0.5 * tdg - m.alpha * T00 * da[j]);
+    }
+    S[4] = -as * (T0[0] * da[0] + T0[1] * da[1] + T0[2] * da[2]);
+  } else {
+    const double* be = m.beta;
+    double blw[3], T0low[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) blw[i] = m.g[sidx(i, 0)] * be[0] + m.g[sidx(i, 1)] * be[1] + m.g[sidx(i, 2)] * be[2];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+      T0low[i] = T00 * blw[i] + T0[0] * m.g[sidx(0, i)] + T0[1] * m.g[sidx(1, i)] + T0[2] * m.g[sidx(2, i)];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      double bbdg = 0.0, tdg = 0.0, t0bdg = 0.0, t0db = 0.0;
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        t0db += T0low[i] * db[j][i];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          const double dgik = dg[j][sidx(i, k)];
+          bbdg += be[i] * be[k] * dgik;
+          tdg += Tij[sidx(i, k)] * dgik;
+          t0bdg += T0[i] * be[k] * dgik;
+        }
+      }
+      S[1 + j] = as * (T00 * (0.5 * bbdg - m.alpha * da[j]) + t0bdg + t0db + 0.5 * tdg);
+    }
+    double K[6];
+    const double i2a = 0.5 * ia;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = i; j < 3; ++j) {
+        double t = 0.0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) t += m.g[sidx(j, k)] * db[i][k] + m.g[sidx(i, k)] * db[j][k] + be[k] * dg[k][sidx(i, j)];
+        K[sidx(i, j)] = t * i2a;
+      }
+    double bbK = 0.0, bda = 0.0, t0i = 0.0, tK = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      bda += be[i] * da[i];
+      double bK = 0.0;
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        bbK += be[i] * be[j] * K[sidx(i, j)];
+        bK += be[j] * K[sidx(i, j)];
+        tK += Tij[sidx(i, j)] * K[sidx(i, j)];
+      }
+      t0i += T0[i] * (2.0 * bK - da[i]);
+    }
+    S[4] = as * (T00 * (bbK - bda) + t0i + tK);
+  }
+}
+
+// ---------------------------------------------------------------- prim -> cons at a cell (FP64)
+
+__device__ __forceinline__ void p2c_cell(const double* g, double sqrtg, double gm1, const double* P, double U[8]) {
+  double vlow[3], Blow[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    vlow[i] = g[sidx(i, 0)] * P[1] + g[sidx(i, 1)] * P[2] + g[sidx(i, 2)] * P[3];
+    Blow[i] = g[sidx(i, 0)] * P[5] + g[sidx(i, 1)] * P[6] + g[sidx(i, 2)] * P[7];
+  }
+  const double v2 = vlow[0] * P[1] + vlow[1] * P[2] + vlow[2] * P[3];
+  const double iW = sqrt(1.0 - v2);
+  const double W = 1.0 / iW;
+  const double B2 = Blow[0] * P[5] + Blow[1] * P[6] + Blow[2] * P[7];
+  const double Bv = Blow[0] * P[1] + Blow[1] * P[2] + Blow[2] * P[3];
+  const double ab0 = W * Bv;
+  const double b2 = (B2 + ab0 * ab0) * (iW * iW);
+  const double p = gm1 * P[0] * P[4];
+  const double rhohs = P[0] * (1.0 + P[4]) + p + b2;
+  const double Ps = p + 0.5 * b2;
+  const double W2 = W * W;
+  U[0] = sqrtg * P[0] * W;
+#pragma unroll
+  for (int j = 0; j < 3; ++j) U[1 + j] = sqrtg * (rhohs * W2 * vlow[j] - ab0 * (Blow[j] * iW + ab0 * vlow[j]));
+  U[4] = sqrtg * (rhohs * W2 - Ps - ab0 * ab0) - U[0];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) U[5 + k] = sqrtg * P[5 + k];
+}
+
+// ---------------------------------------------------------------- con2prim (FP64)
+
+enum { C2P_OK = 0, C2P_FLOOR = 1, C2P_NOCONV = 2, C2P_UNPHYS = 3, C2P_NONFINITE = 4, C2P_FALLBACK = 5 };
+
+struct C2PIn {
+  double Dt, St[3], taut, B[3];
+  double S2, B2, SB;
+};
+
+__device__ __forceinline__ bool dfinite(double x) { return x - x == 0.0; }
+
+// 3D Newton-Raphson in (W, z = rho h W^2, T = p / rho) (Sec. II C).  With
+// B.v = S.B / z and S_j = (z + B^2) v_j - (B.v) B_j the three equations are
+//   f1 = S^2 - (z + B^2)^2 (1 - 1/W^2) + (S.B)^2 (2 z + B^2) / z^2
+//   f2 = tau + D - z - B^2 + D T / W + B^2 / (2 W^2) + (S.B)^2 / (2 z^2)
+//   f3 = z - D W (1 + Gamma T / (Gamma - 1)).
+__device__ bool c2p_newton(const C2PIn& c, const KPhys& ph, double& W, double& z, double& T) {
+  const double gf = ph.gf;
+  const double SB2 = c.SB * c.SB;
+  for (int it = 0; it < ph.c2p_maxit; ++it) {
+    const double zB = z + c.B2;
+    const double iW = 1.0 / W;
+    const double iW2 = iW * iW;
+    const double iz = 1.0 / z;
+    const double iz2 = iz * iz;
+    const double om = 1.0 - iW2;
+    const double f1 = c.S2 - zB * zB * om + SB2 * (2.0 * z + c.B2) * iz2;
+    const double f2 = c.taut + c.Dt - z - c.B2 + c.Dt * T * iW + 0.5 * c.B2 * iW2 + 0.5 * SB2 * iz2;
+    const double hW = 1.0 + gf * T;
+    const double f3 = z - c.Dt * W * hW;
+    const double J11 = -2.0 * zB * zB * iW2 * iW;
+    const double J12 = -2.0 * zB * om - 2.0 * SB2 * zB * iz2 * iz;
+    const double J21 = -c.Dt * T * iW2 - c.B2 * iW2 * iW;
+    const double J22 = -1.0 - SB2 * iz2 * iz;
+    const double J23 = c.Dt * iW;
+    const double J31 = -c.Dt * hW;
+    const double J33 = -c.Dt * W * gf;
+    // J13 = 0, J32 = 1: Cramer's rule on J dx = -f
+    const double m1 = J22 * J33 - J23;        // minor of J11
+    const double m2 = J21 * J33 - J23 * J31;  // minor of J12
+    const double det = J11 * m1 - J12 * m2;
+    const double id = 1.0 / det;
+    const double r1 = -f1, r2 = -f2, r3 = -f3;
+    const double d1 = (r1 * m1 - J12 * (r2 * J33 - J23 * r3)) * id;
+    const double d2 = (J11 * (r2 * J33 - J23 * r3) - r1 * m2) * id;
+    const double d3 = (J11 * (J22 * r3 - r2) - J12 * (J21 * r3 - r2 * J31) + r1 * (J21 - J22 * J31)) * id;
+    W += d1;
+    z += d2;
+    T += d3;
+    if (!(dfinite(W) && dfinite(z) && dfinite(T))) return false;
+    const double err = fmax(fabs(d1 / W), fmax(fabs(d2 / z), fabs(d3 / T)));
+    if (err < ph.c2p_tol) return true;
+  }
+  return false;
+}
+
+// Newman-Hamlin map p -> p' (Sec. II C): the largest root x = z + B^2 of
+// x^3 - (E + p + B^2/2) x^2 + (B^2 S^2 - (S.B)^2)/2 = 0, E = tau + D, then
+// 1/W^2 = 1 - (S^2 + (S.B)^2 (2z + B^2) / z^2) / x^2 and the Gamma-law
+// p' = (Gamma - 1)/Gamma (z/W^2 - D/W).
+__device__ bool nh_map(const C2PIn& c, const KPhys& ph, double p, double& pn, double& W, double& z) {
+  const double E = c.taut + c.Dt;
+  const double dd = fmax(0.0, 0.5 * (c.B2 * c.S2 - c.SB * c.SB));
+  const double a = -(E + p + 0.5 * c.B2);
+  double x = -a;  // f(-a) = dd >= 0 and f is convex there: Newton descends onto the root
+  for (int it = 0; it < 100; ++it) {
+    const double f = x * x * (x + a) + dd;
+    const double fp = x * (3.0 * x + 2.0 * a);
+    const double dx = f / fp;
+    x -= dx;
+    if (!(fabs(dx) > 1e-15 * fabs(x))) break;
+  }
+  z = x - c.B2;
+  if (!(z > 0.0)) return false;
+  const double iW2 = 1.0 - (c.S2 + c.SB * c.SB * (2.0 * z + c.B2) / (z * z)) / (x * x);
+  if (!(iW2 > 0.0)) return false;
+  const double iW = sqrt(iW2);
+  W = 1.0 / iW;
+  pn = (ph.gm1 / ph.gam) * (z * iW2 - c.Dt * iW);
+  return dfinite(pn);
+}
+
+// Fixed-point iteration on the pressure with Aitken extrapolation on every
+// third iterate; returns the (W, z, T) that seed a Newton polish.
+__device__ bool c2p_newman(const C2PIn& c, const KPhys& ph, double p0, double& W, double& z, double& T) {
+  double s1 = p0, s2 = p0;
+  for (int k = 0; k < ph.c2p_maxit; ++k) {
+    double pn;
+    if (!nh_map(c, ph, s2, pn, W, z)) return false;
+    if (!(pn > 0.0)) return false;
+    if (fabs(pn - s2) <= ph.c2p_tol * fabs(pn)) {
+      T = pn * W / c.Dt;
+      return true;
+    }
+    if ((k + 1) % 3 == 0) {
+      const double den = pn - 2.0 * s2 + s1;
+      if (den != 0.0) {
+        const double pa = pn - (pn - s2) * (pn - s2) / den;
+        if (pa > 0.0 && dfinite(pa)) pn = pa;
+      }
+    }
+    s1 = s2;
+    s2 = pn;
+  }
+  return false;
+}
+
+__device__ int c2p_recover(const C2PIn& c, const double* g, const double* gi, double gm1, double W, double z, double T,
+                           double* P) {
+  const double izB = 1.0 / (z + c.B2);
+  const double sbz = c.SB / z;
+  double vlow[3], v[3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j)
+    vlow[j] = (c.St[j] + sbz * (g[sidx(j, 0)] * c.B[0] + g[sidx(j, 1)] * c.B[1] + g[sidx(j, 2)] * c.B[2])) * izB;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) v[i] = gi[sidx(i, 0)] * vlow[0] + gi[sidx(i, 1)] * vlow[1] + gi[sidx(i, 2)] * vlow[2];
+  const double v2 = vlow[0] * v[0] + vlow[1] * v[1] + vlow[2] * v[2];
+  const double rho = c.Dt / W;
+  if (!(W >= 1.0) || !(z > 0.0) || !(T > 0.0) || !(rho > 0.0) || !(v2 < 1.0)) return C2P_UNPHYS;
+  P[0] = rho;
+  P[1] = v[0];
+  P[2] = v[1];
+  P[3] = v[2];
+  P[4] = T / gm1;
+  P[5] = c.B[0];
+  P[6] = c.B[1];
+  P[7] = c.B[2];
+  return C2P_OK;
+}
+
+// Atmosphere (Sec. IV, TOV test): rho_atm, v = 0, polytropic p, B kept; U rewritten.
+__device__ __forceinline__ void c2p_atmosphere(const double* g, double sqrtg, const KPhys& ph, double U[8], double P[8]) {
+  const double is = 1.0 / sqrtg;
+  P[0] = ph.rho_atm;
+  P[1] = P[2] = P[3] = 0.0;
+  P[4] = ph.eps_atm;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) P[5 + k] = U[5 + k] * is;
+  p2c_cell(g, sqrtg, ph.gm1, P, U);
+}
+
+// Full recovery of one cell: U (in/out: atmosphere rewrites it), P (guess in, result out).
+__device__ int c2p_cell(const double* g, const double* gi, double sqrtg, const KPhys& ph, double U[8], double P[8]) {
+  bool fin = true;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) fin = fin && dfinite(U[q]);
+  if (!fin) {
+#pragma unroll
+    for (int k = 5; k < 8; ++k) U[k] = dfinite(U[k]) ? U[k] : 0.0;
+    c2p_atmosphere(g, sqrtg, ph, U, P);
+    return C2P_NONFINITE;
+  }
+  const double is = 1.0 / sqrtg;
+  C2PIn c;
+  c.Dt = U[0] * is;
+  if (c.Dt < ph.rho_atm) {
+    c2p_atmosphere(g, sqrtg, ph, U, P);
+    return C2P_FLOOR;
+  }
+#pragma unroll
+  for (int j = 0; j < 3; ++j) c.St[j] = U[1 + j] * is;
+  c.taut = U[4] * is;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) c.B[k] = U[5 + k] * is;
+  double S2 = 0.0, B2 = 0.0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      S2 += gi[sidx(i, j)] * c.St[i] * c.St[j];
+      B2 += g[sidx(i, j)] * c.B[i] * c.B[j];
+    }
+  c.S2 = S2;
+  c.B2 = B2;
+  c.SB = c.St[0] * c.B[0] + c.St[1] * c.B[1] + c.St[2] * c.B[2];
+  // seed from the previous primitives
+  double W, z, T, p0;
+  {
+    double v2 = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) v2 += g[sidx(i, j)] * P[1 + i] * P[1 + j];
+    const bool ok = dfinite(v2) && v2 < 1.0 && P[0] > 0.0 && P[4] > 0.0 && dfinite(P[0]) && dfinite(P[4]);
+    if (ok) {
+      W = 1.0 / sqrt(1.0 - v2);
+      p0 = ph.gm1 * P[0] * P[4];
+      z = (P[0] + P[0] * P[4] + p0) * W * W;
+      T = p0 / P[0];
+    } else {
+      W = 1.0;
+      T = ph.gm1 * fmax(c.taut - 0.5 * B2, 1e-10 * c.Dt) / c.Dt;
+      z = c.Dt * (1.0 + ph.gf * T);
+      p0 = c.Dt * T;
+    }
+  }
+  double Pn[8];
+  int st = C2P_NOCONV;
+  {
+    double W1 = W, z1 = z, T1 = T;
+    if (c2p_newton(c, ph, W1, z1, T1)) st = c2p_recover(c, g, gi, ph.gm1, W1, z1, T1, Pn);
+  }
+  if (st != C2P_OK) {
+    double W2, z2, T2;
+    int st2 = C2P_NOCONV;
+    if (c2p_newman(c, ph, p0, W2, z2, T2) && c2p_newton(c, ph, W2, z2, T2))
+      st2 = c2p_recover(c, g, gi, ph.gm1, W2, z2, T2, Pn);
+    if (st2 == C2P_OK) st = C2P_FALLBACK;
+    else if (st == C2P_NOCONV) st = st2;
+  }
+  if (st != C2P_OK && st != C2P_FALLBACK) {
+    c2p_atmosphere(g, sqrtg, ph, U, P);
+    return st;
+  }
+  if (Pn[0] < ph.rho_atm) {
+    c2p_atmosphere(g, sqrtg, ph, U, P);
+    return C2P_FLOOR;
+  }
+#pragma unroll
+  for (int q = 0; q < 8; ++q) P[q] = Pn[q];
+  return st;
+}
+
+}  // namespace gk

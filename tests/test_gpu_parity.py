@@ -1,0 +1,288 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Bar: per-field relative L-infinity (max |gpu - oracle| / max |oracle| over
+interior cells) <= 1e-12 in FP64, integer outputs (con2prim status, failure
+counts) bit-exact.  Small problems are compared everywhere; the workloads at
+full size are compared on sampled cells, each computed by the oracle on its
+domain of dependence.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from paper_2210_17509_amd import inputs as I
+from tests import gpu_helpers as H
+from tests import problems as T
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2210_17509_amd import grmhd  # noqa: F401  (fails loudly if the library is missing)
+
+
+def _ragged(recon=I.RECON_WENO5):
+    bc = (I.BC_OUTFLOW, I.BC_OUTFLOW, I.BC_PERIODIC, I.BC_PERIODIC, I.BC_OUTFLOW, I.BC_OUTFLOW)
+    def f(X, Y, Z):
+        return I.flat_fields(np.random.default_rng(77), X, Y, Z, 5.0 / 3.0, jump_at=0.4)
+    return T.build((19, 13, 10), f, bc=bc, params=I.Params(recon=recon))
+
+
+def _shifted():
+    met = T.conformal_metric(lambda X, Y, Z: 1.0 + 0.05 * np.sin(2 * np.pi * X) * np.cos(2 * np.pi * Z),
+                             alpha_fn=lambda X, Y, Z: 0.9 + 0.05 * np.cos(2 * np.pi * Y),
+                             beta_fn=lambda X, Y, Z: [0.1 * np.sin(2 * np.pi * Y), 0.05 + 0 * X,
+                                                      -0.08 * np.cos(2 * np.pi * X)])
+    return T.build((12, 10, 9), T.smooth_fields(5, 2.0), met, params=I.Params(recon=I.RECON_WENO5, eos_gamma=2.0))
+
+
+def _oned():
+    bc = (I.BC_OUTFLOW, I.BC_OUTFLOW) + (I.BC_PERIODIC,) * 4
+    def f(X, Y, Z):
+        left = X < 0.5
+        row = [np.where(left, 1.0, 0.125), 0 * X, 0 * X, 0 * X, np.where(left, 1.0, 0.8), 0.5 + 0 * X,
+               np.where(left, 1.0, -1.0), 0 * X]
+        return row
+    return T.build((40, 1, 1), f, bc=bc, dx=(1 / 40, 1.0, 1.0), params=I.Params(recon=I.RECON_MINMOD, eos_gamma=2.0),
+                   dt=0.25 / 40)
+
+
+CASES = {
+    "config0_minmod_jump": lambda: I.config0(n=16),
+    "config1_weno5_curved": lambda: I.config1(n=24),
+    "config4_wenoz": lambda: I.config4(n=16),
+    "ragged_weno5": _ragged,
+    "ragged_minmod_ng2": lambda: _ragged_ng2(),
+    "shifted_metric": _shifted,
+    "oned_periodic_yz": _oned,
+}
+
+
+def _ragged_ng2():
+    bc = (I.BC_PERIODIC,) * 2 + (I.BC_OUTFLOW,) * 4
+    def f(X, Y, Z):
+        return I.flat_fields(np.random.default_rng(78), X, Y, Z, 5.0 / 3.0, jump_at=0.6)
+    return T.build((11, 7, 17), f, bc=bc, ng=2, params=I.Params(recon=I.RECON_MINMOD))
+
+
+def _assert_close(gpu, ref, tol=TOL, what=""):
+    r = H.rel_linf(gpu, ref)
+    assert np.all(r <= tol), f"{what} rel L-inf per field {r}"
+    return r
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_prim2con_parity(orc, case):
+    prob = CASES[case]()
+    d = H.Dev(prob)
+    Ug = H.interior_fields(prob, d.host(d.U))
+    Uo = H.interior_fields(prob, orc.prim2con(prob))
+    _assert_close(Ug, Uo, 1e-14, case)
+
+
+@pytest.mark.parametrize("case", ["config1_weno5_curved", "ragged_weno5", "shifted_metric"])
+def test_con2prim_parity(orc, case):
+    """Perturbed conserved state, previous primitives as the guess; P and the status codes."""
+    import torch
+    prob = CASES[case]()
+    Uo = orc.prim2con(prob)
+    rng = np.random.default_rng(1)
+    Uo = Uo * (1.0 + 1e-3 * rng.standard_normal(Uo.shape))
+    Po = prob.P.copy()
+    st_o, nf_o = orc.con2prim(prob, Uo_c := Uo.copy(), Po)
+    d = H.Dev(prob)
+    d.U.copy_(torch.as_tensor(Uo))
+    status = torch.zeros(prob.cell_stride, dtype=torch.int32, device="cuda")
+    H.G().grmhd_con2prim(d.dom, d.par, d.met, d.U, d.P, status, d.nfail)
+    _assert_close(H.interior_fields(prob, d.host(d.P)), H.interior_fields(prob, Po), TOL, case)
+    _assert_close(H.interior_fields(prob, d.host(d.U)), H.interior_fields(prob, Uo_c), 1e-15, case)
+    sg = d.host(status)
+    mask = np.concatenate([I.interior_mask(b).ravel() for b in prob.boxes])
+    np.testing.assert_array_equal(sg[:mask.size][mask], st_o[:mask.size][mask])
+    assert int(d.host(d.nfail)[0]) == nf_o
+
+
+def test_con2prim_failures_and_atmosphere(orc):
+    """Unrecoverable and floor states: identical statuses, atmosphere values and U rewrite."""
+    import torch
+    prob = I.config1(n=12)
+    U = orc.prim2con(prob)
+    bx = prob.boxes[0]
+    Uv = prob.box_view(U, 0)
+    g = bx.ng
+    Uv[1, g + 2, g + 3, g + 4] = 50.0 * (Uv[4, g + 2, g + 3, g + 4] + Uv[0, g + 2, g + 3, g + 4])  # superluminal
+    Uv[0, g + 5, g + 5, g + 5] = 1e-14                                                              # below floor
+    Uv[4, g + 1, g + 7, g + 2] = np.nan                                                             # non-finite
+    Po = prob.P.copy()
+    Uo = U.copy()
+    st_o, nf_o = orc.con2prim(prob, Uo, Po)
+    d = H.Dev(prob)
+    d.U.copy_(torch.as_tensor(U))
+    status = torch.zeros(prob.cell_stride, dtype=torch.int32, device="cuda")
+    H.G().grmhd_con2prim(d.dom, d.par, d.met, d.U, d.P, status, d.nfail)
+    m = I.interior_mask(bx).ravel()
+    np.testing.assert_array_equal(d.host(status)[m], st_o[m])
+    assert set(np.unique(st_o[m])) >= {0, 1, 4}
+    assert int(d.host(d.nfail)[0]) == nf_o >= 2
+    _assert_close(H.interior_fields(prob, d.host(d.P)), H.interior_fields(prob, Po), TOL)
+    _assert_close(H.interior_fields(prob, d.host(d.U)), H.interior_fields(prob, Uo), TOL)
+
+
+@pytest.mark.parametrize("tile", [0, 1, 2])
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_rhs_parity(orc, case, tile):
+    prob = CASES[case]()
+    d = H.Dev(prob, tile=tile)
+    dg = H.interior_fields(prob, d.host(d.rhs()))
+    Uo = orc.prim2con(prob)
+    do, rate_o, nf_o = orc.rhs(prob, Uo, prob.P.copy())
+    _assert_close(dg, H.interior_fields(prob, do), TOL, case)
+    assert float(d.host(d.rate)[0]) == pytest.approx(rate_o, rel=1e-12)
+    assert int(d.host(d.nfail)[0]) == nf_o
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_rk_step_parity(orc, case):
+    prob = CASES[case]()
+    steps = 2 if case in ("config0_minmod_jump", "oned_periodic_yz") else 1
+    d = H.Dev(prob)
+    d.step(steps)
+    Uo, Po = orc.prim2con(prob), prob.P.copy()
+    rate_o, nf_o = orc.rk_step(prob, Uo, Po, steps=steps)
+    _assert_close(H.interior_fields(prob, d.host(d.U)), H.interior_fields(prob, Uo), TOL, case + " U")
+    _assert_close(H.interior_fields(prob, d.host(d.P)), H.interior_fields(prob, Po), TOL, case + " P")
+    assert float(d.host(d.rate)[0]) == pytest.approx(rate_o, rel=1e-12)
+    assert int(d.host(d.nfail)[0]) == nf_o
+
+
+def test_ssprk2_and_checkpoints(orc):
+    import torch
+    prob = I.config1(n=20)
+    d = H.Dev(prob)
+    ck = torch.zeros((2,) + tuple(d.U.shape), dtype=torch.float64, device="cuda")
+    d.step(1, scheme=1, ckpt=ck)
+    Uo, Po = orc.prim2con(prob), prob.P.copy()
+    _, _, cko = orc.rk_step(prob, Uo, Po, scheme=1, ckpt=True)
+    _assert_close(H.interior_fields(prob, d.host(d.U)), H.interior_fields(prob, Uo), TOL)
+    ckg = d.host(ck)
+    for s in range(2):
+        _assert_close(H.interior_fields(prob, ckg[s]), H.interior_fields(prob, cko[0][s].reshape(8, -1)), TOL)
+
+
+@pytest.mark.parametrize("recon", [I.RECON_MINMOD, I.RECON_WENO5, I.RECON_WENOZ])
+def test_uniform_state_bitwise(recon):
+    state = [0.7, 0.3, -0.2, 0.1, 1.2, 0.5, -0.4, 0.8]
+    bc = (I.BC_OUTFLOW, I.BC_OUTFLOW, I.BC_PERIODIC, I.BC_PERIODIC, I.BC_OUTFLOW, I.BC_PERIODIC)
+    prob = T.build((21, 9, 6), T.uniform_fields(state), bc=bc, params=I.Params(recon=recon))
+    d = H.Dev(prob)
+    U0 = d.host(d.U).copy()
+    d.step(2)
+    np.testing.assert_array_equal(H.interior_fields(prob, d.host(d.U)), H.interior_fields(prob, U0))
+    Pi = H.interior_fields(prob, d.host(d.P))
+    assert np.all(Pi == Pi[:, :1])
+
+
+def test_conservation_periodic():
+    prob = T.build((24, 20, 16), T.smooth_fields(4, 5.0 / 3.0), params=I.Params(recon=I.RECON_WENO5))
+    d = H.Dev(prob)
+    dd = H.interior_fields(prob, d.host(d.rhs()))
+    for q in range(8):
+        assert abs(dd[q].sum()) <= 1e-13 * np.abs(dd[q]).sum()
+
+
+def test_config0_full_size(orc):
+    """64^3 minmod with the jump: every interior cell against the oracle."""
+    prob = I.config0()
+    d = H.Dev(prob)
+    d.step(1)
+    Uo, Po = orc.prim2con(prob), prob.P.copy()
+    rate_o, nf_o = orc.rk_step(prob, Uo, Po)
+    _assert_close(H.interior_fields(prob, d.host(d.U)), H.interior_fields(prob, Uo), TOL, "U")
+    _assert_close(H.interior_fields(prob, d.host(d.P)), H.interior_fields(prob, Po), TOL, "P")
+    assert float(d.host(d.rate)[0]) == pytest.approx(rate_o, rel=1e-12)
+    assert int(d.host(d.nfail)[0]) == nf_o == 0
+
+
+def _sampled(orc, prob, d, nsample, seed, tol):
+    bx = prob.boxes[0]
+    g = bx.ng
+    n = bx.n
+    rng = np.random.default_rng(seed)
+    cells = [tuple(int(rng.integers(0, n[q])) for q in range(3)) for _ in range(nsample)]
+    cells += [(0, 0, 0), (n[0] - 1, n[1] - 1, n[2] - 1), (n[0] // 2, n[1] // 2, n[2] // 2)]
+    Ug = prob.box_view(d.host(d.U), 0)
+    Pg = prob.box_view(d.host(d.P), 0)
+    ref_U, ref_P, got_U, got_P = [], [], [], []
+    for c in cells:
+        sub, ci = H.sub_problem(prob, c, radius=9)
+        Us, Ps = orc.prim2con(sub), sub.P.copy()
+        orc.rk_step(sub, Us, Ps)
+        ref_U.append(sub.box_view(Us, 0)[:, ci[2] + g, ci[1] + g, ci[0] + g])
+        ref_P.append(sub.box_view(Ps, 0)[:, ci[2] + g, ci[1] + g, ci[0] + g])
+        got_U.append(Ug[:, c[2] + g, c[1] + g, c[0] + g])
+        got_P.append(Pg[:, c[2] + g, c[1] + g, c[0] + g])
+    _assert_close(np.array(got_U).T, np.array(ref_U).T, tol, "sampled U")
+    _assert_close(np.array(got_P).T, np.array(ref_P).T, tol, "sampled P")
+
+
+def test_config1_full_size_sampled(orc):
+    """256^3 curved WENO5 step in the benchmark's launch configuration, sampled cells."""
+    prob = I.config1()
+    d = H.Dev(prob)
+    d.step(1)
+    assert int(d.host(d.nfail)[0]) == 0
+    _sampled(orc, prob, d, 24, 5, TOL)
+
+
+def test_config1_384_sampled(orc):
+    """Largest single-box size in the workloads: 384^3 curved WENO5 (FP64)."""
+    prob = I.config1(n=384, seed=I.SEED_BASE + 3)
+    d = H.Dev(prob)
+    d.step(1)
+    _sampled(orc, prob, d, 12, 6, TOL)
+
+
+def test_mixed_precision_error_bound(orc):
+    """FP32 reconstruction + HLLE, FP64 elsewhere: one step of the curved WENO5 workload
+    stays within 2e-6 relative L-infinity of the FP64 oracle per field."""
+    prob = I.config1(n=32, precision=I.PREC_MIXED)
+    d = H.Dev(prob)
+    d.step(1)
+    Uo, Po = orc.prim2con(prob), prob.P.copy()
+    orc.rk_step(prob, Uo, Po)
+    r = _assert_close(H.interior_fields(prob, d.host(d.U)), H.interior_fields(prob, Uo), 2e-6, "mixed U")
+    assert r.max() > 1e-12  # it really ran in FP32
+    _assert_close(H.interior_fields(prob, d.host(d.P)), H.interior_fields(prob, Po), 2e-6, "mixed P")
+
+
+def test_error_returns_on_device():
+    import torch
+    g = H.G()
+    prob = I.config1(n=8)
+    d = H.Dev(prob)
+    small = torch.zeros(8, dtype=torch.float64, device="cuda")
+    with pytest.raises(g.GrmhdError) as e:
+        g.grmhd_rk_step(d.dom, d.par, d.met, d.U, d.P, prob.dt, ws=small)
+    assert e.value.code == g.GRMHD_EWORKSPACE
+    with pytest.raises(g.GrmhdError) as e:
+        g.grmhd_rk_step(d.dom, d.par, d.met, d.U, d.P, -1.0)
+    assert e.value.code == g.GRMHD_EINVAL
+    # the host box list changed after prepare: refused until prepared again
+    d.dom._boxes[0].n[0] += 1
+    with pytest.raises(g.GrmhdError) as e:
+        g.grmhd_rhs(d.dom, d.par, d.met, d.U, d.P, torch.zeros_like(d.U))
+    assert "changed" in str(e.value)
+    d.dom._boxes[0].n[0] -= 1
+    g.grmhd_rhs(d.dom, d.par, d.met, d.U, d.P, torch.zeros_like(d.U))
+    # WENO needs 3 ghost layers
+    prob2 = T.build((8, 8, 8), T.smooth_fields(1, 5.0 / 3.0), ng=2, params=I.Params(recon=I.RECON_WENO5))
+    d2 = H.Dev(prob2)
+    with pytest.raises(g.GrmhdError) as e:
+        g.grmhd_rhs(d2.dom, d2.par, d2.met, d2.U, d2.P, torch.zeros_like(d2.U))
+    assert "ghost" in str(e.value)
