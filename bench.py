@@ -17,7 +17,12 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
-FP64_VECTOR_PEAK_TFLOPS = 78.6  # 256 CU x 2.4 GHz x 128 FP64 flop/clk (FMA = 2)
+FP64_VECTOR_PEAK_TFLOPS = 78.6  # 256 CU x 2.4 GHz x 64 FP64 lanes x 2 (FMA = 2 flops)
+
+# Arithmetic of one stage-kernel launch per interior cell (3 faces + the cell's
+# metric, sources, divergence and stage combine; +, -, *, /, sqrt = 1 flop each),
+# counted by running the method's routines on an op-counting scalar.
+FLOPS_PER_CELL = {0: 2364, 1: 5292, 2: 5484}   # minmod, WENO5, WENO5-Z
 
 WORKLOADS = {
     # name: (builder kwargs, description)
@@ -121,8 +126,9 @@ def main():
     st_ms, st_n = times["stage"]
     c2p_ms, c2p_n = times["con2prim"]
     avg_stage_s = st_ms / 1e3 / max(st_n, 1)
-    bytes_per_launch = stage_bytes_per_cell() * ncell
-    achieved = bytes_per_launch / avg_stage_s / 1e9
+    flops_per_launch = FLOPS_PER_CELL[prob.params.recon] * ncell
+    achieved = flops_per_launch / avg_stage_s / 1e12
+    hbm_gbs = stage_bytes_per_cell() * ncell / avg_stage_s / 1e9
     out = {
         "metric": "GRMHD zone-updates/s per RK stage",
         "value": value,
@@ -140,8 +146,10 @@ def main():
                    "n_fail": int(nfail.item())},
         "kernels": {"stage_ms_avg": st_ms / max(st_n, 1), "stage_launches": st_n,
                     "con2prim_ms_avg": c2p_ms / max(c2p_n, 1), "con2prim_launches": c2p_n},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
+                     "kernel": "k_stage", "flops_per_cell": FLOPS_PER_CELL[prob.params.recon],
+                     "algorithmic_hbm_GBs": hbm_gbs, "algorithmic_hbm_frac": hbm_gbs / HBM_PEAK_GBS},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.workload)

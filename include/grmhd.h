@@ -171,6 +171,27 @@ int grmhd_rk_step(const grmhd_domain* dom, const grmhd_params* par, const grmhd_
                   double* U, double* P, double dt, int32_t scheme, double* stage_ckpt,
                   double* max_rate, int64_t* n_fail, void* ws, size_t ws_bytes, void* stream);
 
+/* Vector-Jacobian product of con2prim on interior cells: gU = (dP/dU)^T gP,
+ * through the implicit-function theorem (con2prim inverts Eqs. (p2c1)-(p2c4),
+ * so dP/dU = (dU/dP)^{-1}, evaluated at the primitives P).  FP64. */
+int grmhd_con2prim_adjoint(const grmhd_domain* dom, const grmhd_params* par, const grmhd_metric* met,
+                           const double* P, const double* gP, double* gU, void* stream);
+
+/* Adjoint of one grmhd_rk_step: gU_in = (dU^{n+1}/dU^n)^T gU_out on interior
+ * cells, from the stage checkpoints that grmhd_rk_step wrote (U^n and the
+ * stage states after their con2prim).  Per stage, in reverse: con2prim of the
+ * checkpoint (P is the guess on input and scratch; it ends as the primitives
+ * of U^n), then the transposed flux divergence, HLLE and reconstruction
+ * (scattered with FP64 atomics, so the last bits can vary between runs), the
+ * source-term VJP, con2prim through the implicit-function theorem and the
+ * transposed stage combine.  Branches (minmod, max/min of the wave speeds,
+ * positivity fallback) follow the forward choice; atmosphere resets are not
+ * differentiated.  FP64 whatever par->precision says.
+ * ws: grmhd_workspace_bytes(..., for_adjoint = 1) bytes. */
+int grmhd_rk_step_adjoint(const grmhd_domain* dom, const grmhd_params* par, const grmhd_metric* met,
+                          const double* stage_ckpt, double* P, double dt, int32_t scheme, const double* gU_out,
+                          double* gU_in, void* ws, size_t ws_bytes, void* stream);
+
 /* Workspace bytes for grmhd_rk_step (for_adjoint = 0) or
  * grmhd_rk_step_adjoint (for_adjoint = 1). */
 size_t grmhd_workspace_bytes(const grmhd_domain* dom, const grmhd_params* par, int32_t scheme,

@@ -79,6 +79,7 @@ def lib():
         L.orc_recon_line.argtypes = [pp, ctypes.c_int, _D, _D, _D, ctypes.c_int]
         L.orc_point_sources.argtypes = [_D, ctypes.c_double, _D, _D, _D, _D, _D, ctypes.c_double, ctypes.c_int,
                                         _D]
+        L.orc_count_ops.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_long)]
         _lib = L
     return _lib
 
@@ -309,3 +310,10 @@ def rk_step_jvp(prob, U, dU, P, dt=None, scheme=0, steps=1):
     L.orc_rk_step_jvp(ctypes.byref(make_box(prob.boxes[0])), ctypes.byref(par), _p(a), _p(be), _p(g), _p(Ub),
                       _p(dUb), _p(Pb), float(dt), int(scheme), int(steps))
     return Ub, dUb, Pb
+
+
+def count_ops(recon):
+    """Arithmetic of the method per face and per cell: dict of (add, mul, div, sqrt)."""
+    out = (ctypes.c_long * 8)()
+    lib().orc_count_ops(int(recon), out)
+    return {"face": tuple(out[0:4]), "cell": tuple(out[4:8])}

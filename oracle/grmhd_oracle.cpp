@@ -94,6 +94,45 @@ inline bool finite(const Dual& a) { return std::isfinite(a.v) && std::isfinite(a
 using std::fabs;
 using std::sqrt;
 
+// Op-counting scalar: every +, -, *, / and sqrt on it is tallied (comparisons
+// and fabs are not floating-point work).  Used to count the method's
+// arithmetic per face and per cell.
+struct OpTally { long add, mul, div, sqrt; };
+static OpTally g_tally = {0, 0, 0, 0};
+struct Cnt {
+  double v;
+  Cnt() : v(0) {}
+  Cnt(double a) : v(a) {}
+};
+inline Cnt operator+(Cnt a, Cnt b) { ++g_tally.add; return Cnt(a.v + b.v); }
+inline Cnt operator-(Cnt a, Cnt b) { ++g_tally.add; return Cnt(a.v - b.v); }
+inline Cnt operator-(Cnt a) { return Cnt(-a.v); }
+inline Cnt operator*(Cnt a, Cnt b) { ++g_tally.mul; return Cnt(a.v * b.v); }
+inline Cnt operator/(Cnt a, Cnt b) { ++g_tally.div; return Cnt(a.v / b.v); }
+inline Cnt operator+(Cnt a, double b) { return a + Cnt(b); }
+inline Cnt operator+(double a, Cnt b) { return Cnt(a) + b; }
+inline Cnt operator-(Cnt a, double b) { return a - Cnt(b); }
+inline Cnt operator-(double a, Cnt b) { return Cnt(a) - b; }
+inline Cnt operator*(Cnt a, double b) { return a * Cnt(b); }
+inline Cnt operator*(double a, Cnt b) { return Cnt(a) * b; }
+inline Cnt operator/(Cnt a, double b) { return a / Cnt(b); }
+inline Cnt operator/(double a, Cnt b) { return Cnt(a) / b; }
+inline Cnt& operator+=(Cnt& a, Cnt b) { a = a + b; return a; }
+inline Cnt& operator-=(Cnt& a, Cnt b) { a = a - b; return a; }
+inline bool operator<(Cnt a, Cnt b) { return a.v < b.v; }
+inline bool operator>(Cnt a, Cnt b) { return a.v > b.v; }
+inline bool operator<=(Cnt a, Cnt b) { return a.v <= b.v; }
+inline bool operator>=(Cnt a, Cnt b) { return a.v >= b.v; }
+inline bool operator<(Cnt a, double b) { return a.v < b; }
+inline bool operator>(Cnt a, double b) { return a.v > b; }
+inline bool operator<=(Cnt a, double b) { return a.v <= b; }
+inline bool operator>=(Cnt a, double b) { return a.v >= b; }
+inline bool operator==(Cnt a, double b) { return a.v == b; }
+inline Cnt sqrt(Cnt a) { ++g_tally.sqrt; return Cnt(std::sqrt(a.v)); }
+inline Cnt fabs(Cnt a) { return Cnt(std::fabs(a.v)); }
+inline double val(const Cnt& a) { return a.v; }
+inline bool finite(const Cnt& a) { return std::isfinite(a.v); }
+
 template <class T> inline T sq(T x) { return x * x; }
 template <class T> inline T tmax(T a, T b) { return (a < b) ? b : a; }
 template <class T> inline T tmin(T a, T b) { return (b < a) ? b : a; }
@@ -1239,6 +1278,122 @@ void orc_point_sources(const double* P, double alpha, const double* beta, const 
     sources_covariant(m, D, P, gam, S);
   else
     sources_3p1(m, D, P, gam, S);
+}
+
+
+// Arithmetic of the method per unit, tallied with the counting scalar on a
+// smooth physical state (zero shift, conformally flat metric):
+//   out[0..3] one face in direction 0: 4-vertex metric averages of alpha and
+//             gamma_ij, det / gamma^dd / sqrt(gamma), reconstruction of 8
+//             fields on both sides, the two positivity checks and HLLE;
+//   out[4..7] one cell: 8-vertex metric averages and inverse, edge-averaged
+//             derivatives of alpha and gamma_ij, the zero-shift source terms,
+//             the divergence of 3 face pairs and the SSPRK stage combine.
+// Each group is (add/sub, mul, div, sqrt).
+void orc_count_ops(int recon, long* out) {
+  Par par;
+  std::memset(&par, 0, sizeof(par));
+  par.recon = recon;
+  par.gam = 5.0 / 3.0;
+  par.weno_eps = 1e-6;
+  par.wenoz_eps = 1e-40;
+  par.wenoz_p = 1;
+  // ---- one face ----
+  g_tally = {0, 0, 0, 0};
+  Cnt stencil[8][6];
+  for (int q = 0; q < 8; ++q)
+    for (int o = 0; o < 6; ++o) stencil[q][o] = Cnt((q == 0 ? 1.0 : (q == 4 ? 1.5 : 0.1)) + 0.01 * o * (q + 1));
+  Cnt v4[7][4];
+  for (int f = 0; f < 7; ++f)
+    for (int c = 0; c < 4; ++c) v4[f][c] = Cnt((f == 0 || f == 1 || f == 4 || f == 6) ? 1.0 + 0.001 * c : 0.0);
+  PMetric<Cnt> m;
+  {
+    Cnt av[7];
+    for (int f = 0; f < 7; ++f) av[f] = 0.25 * ((v4[f][0] + v4[f][1]) + (v4[f][2] + v4[f][3]));
+    m.alpha = av[0];
+    for (int a = 0; a < 3; ++a) m.beta[a] = Cnt(0.0);
+    for (int a = 0; a < 6; ++a) m.g[a] = av[1 + a];
+    // only det, sqrt(gamma) and gamma^dd are needed on a face
+    const Cnt* g = m.g;
+    Cnt cxx = g[3] * g[5] - g[4] * g[4];
+    Cnt cxy = g[2] * g[4] - g[1] * g[5];
+    Cnt cxz = g[1] * g[4] - g[2] * g[3];
+    m.det = g[0] * cxx + g[1] * cxy + g[2] * cxz;
+    m.sqrtg = sqrt(m.det);
+    m.ginv[0] = cxx / m.det;
+  }
+  Cnt PL[8], PR[8];
+  for (int q = 0; q < 8; ++q) recon_face(par, stencil[q], PL[q], PR[q]);
+  (void)state_ok(m, PL);
+  (void)state_ok(m, PR);
+  Cnt Fs[8], xp, xm;
+  hlle(m, PL, PR, par.gam, 0, Fs, xp, xm);
+  out[0] = g_tally.add; out[1] = g_tally.mul; out[2] = g_tally.div; out[3] = g_tally.sqrt;
+  // ---- one cell ----
+  g_tally = {0, 0, 0, 0};
+  Cnt v8[7][8];
+  for (int f = 0; f < 7; ++f)
+    for (int c = 0; c < 8; ++c) v8[f][c] = Cnt((f == 0 || f == 1 || f == 4 || f == 6) ? 1.0 + 0.001 * c : 0.0);
+  PMetric<Cnt> mc;
+  {
+    Cnt av[7];
+    for (int f = 0; f < 7; ++f)
+      av[f] = 0.125 * (((v8[f][0] + v8[f][1]) + (v8[f][2] + v8[f][3])) + ((v8[f][4] + v8[f][5]) + (v8[f][6] + v8[f][7])));
+    mc.alpha = av[0];
+    for (int a = 0; a < 3; ++a) mc.beta[a] = Cnt(0.0);
+    for (int a = 0; a < 6; ++a) mc.g[a] = av[1 + a];
+    metric_finish(mc);
+  }
+  Cnt dal[3], dgm[3][6];
+  const Cnt idx(64.0);
+  for (int e = 0; e < 3; ++e) {
+    Cnt d[7];
+    for (int f = 0; f < 7; ++f) {
+      Cnt s0 = v8[f][1] - v8[f][0], s1 = v8[f][3] - v8[f][2], s2 = v8[f][5] - v8[f][4], s3 = v8[f][7] - v8[f][6];
+      d[f] = 0.25 * ((s0 + s1) + (s2 + s3)) * idx;
+    }
+    dal[e] = d[0];
+    for (int a = 0; a < 6; ++a) dgm[e][a] = d[1 + a];
+  }
+  Cnt Pc[8];
+  for (int q = 0; q < 8; ++q) Pc[q] = stencil[q][2];
+  {
+    // zero-shift static sources: S_Sj = alpha sqrt(g) (-alpha T^00 d_j alpha + T^ik d_j gamma_ik / 2),
+    // S_tau = -alpha sqrt(g) T^0i d_i alpha, with T^{mu nu} from u^mu, b^mu (Eq. (mhd-stress-energy-tensor))
+    PState<Cnt> s;
+    prim_state(mc, Pc, par.gam, s);
+    Cnt ia = Cnt(1.0) / mc.alpha;
+    Cnt u0 = s.W * ia, b0 = s.ab0 * ia * ia;
+    Cnt u[3], b[3];
+    for (int i = 0; i < 3; ++i) {
+      u[i] = s.W * Pc[1 + i];
+      b[i] = (Pc[5 + i] + mc.alpha * b0 * u[i]) / s.W;
+    }
+    Cnt ia2 = ia * ia;
+    Cnt T00 = s.rhohs * u0 * u0 - s.Ps * ia2 - b0 * b0;
+    Cnt T0[3], Tij[6];
+    for (int i = 0; i < 3; ++i) T0[i] = s.rhohs * u0 * u[i] - b0 * b[i];
+    for (int i = 0; i < 3; ++i)
+      for (int j = i; j < 3; ++j) Tij[sym(i, j)] = s.rhohs * u[i] * u[j] + s.Ps * mc.ginv[sym(i, j)] - b[i] * b[j];
+    Cnt as = mc.alpha * mc.sqrtg;
+    Cnt S[8];
+    for (int j = 0; j < 3; ++j) {
+      Cnt t = Cnt(0.0);
+      for (int i = 0; i < 3; ++i)
+        for (int k = 0; k < 3; ++k) t = t + Tij[sym(i, k)] * dgm[j][sym(i, k)];
+      S[1 + j] = as * (0.5 * t - mc.alpha * T00 * dal[j]);
+    }
+    S[4] = Cnt(0.0) - as * (T0[0] * dal[0] + T0[1] * dal[1] + T0[2] * dal[2]);
+    // divergence of 3 face pairs and the stage combine U^n + c ((U_s - U^n) + dt L)
+    Cnt acc[8], Fl(0.3), Fh(0.2), un(1.0), us(1.1), dt(0.01), cs(0.25);
+    for (int q = 0; q < 8; ++q) {
+      acc[q] = (q == 0 || q >= 5) ? Cnt(0.0) : S[q];
+      for (int d = 0; d < 3; ++d) acc[q] = acc[q] + (Fl - Fh) * idx;
+      Cnt o = un + cs * ((us - un) + dt * acc[q]);
+      (void)o;
+    }
+  }
+  out[4] = g_tally.add; out[5] = g_tally.mul; out[6] = g_tally.div; out[7] = g_tally.sqrt;
 }
 
 }  // extern "C"

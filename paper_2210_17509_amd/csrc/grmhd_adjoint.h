@@ -1,0 +1,429 @@
+// Adjoint (vector-Jacobian product) building blocks of the SSPRK step.
+//
+// For L(U) = sum_d (F_lo - F_hi) / dx_d + S(P), P = con2prim(U):
+//   J^T v = (dU/dP)^{-T} [ sum_faces (dF*/dP_stencil)^T Fbar + (dS/dP)^T v ],
+//   Fbar(face between cells c-1, c) = (v_c - v_{c-1}) / dx_d,
+// where con2prim is differentiated through the implicit-function theorem
+// (it inverts prim->cons, so dP/dU = (dU/dP)^{-1}).  Face Jacobians combine a
+// hand-derived gradient of each reconstruction with forward-mode dual numbers
+// (8 tangents per side) through the same side routines the forward kernel
+// runs.  Max/min branches follow the forward choice.
+#pragma once
+
+#include "grmhd_device.h"
+
+namespace gk {
+
+// ---------------------------------------------------------------- dual numbers
+
+template <int N> struct DN {
+  double v;
+  double d[N];
+  __device__ __forceinline__ DN() {}
+  __device__ __forceinline__ DN(double a) : v(a) {
+#pragma unroll
+    for (int k = 0; k < N; ++k) d[k] = 0.0;
+  }
+};
+
+template <int N> __device__ __forceinline__ DN<N> operator+(const DN<N>& a, const DN<N>& b) {
+  DN<N> r;
+  r.v = a.v + b.v;
+#pragma unroll
+  for (int k = 0; k < N; ++k) r.d[k] = a.d[k] + b.d[k];
+  return r;
+}
+template <int N> __device__ __forceinline__ DN<N> operator-(const DN<N>& a, const DN<N>& b) {
+  DN<N> r;
+  r.v = a.v - b.v;
+#pragma unroll
+  for (int k = 0; k < N; ++k) r.d[k] = a.d[k] - b.d[k];
+  return r;
+}
+template <int N> __device__ __forceinline__ DN<N> operator-(const DN<N>& a) {
+  DN<N> r;
+  r.v = -a.v;
+#pragma unroll
+  for (int k = 0; k < N; ++k) r.d[k] = -a.d[k];
+  return r;
+}
+template <int N> __device__ __forceinline__ DN<N> operator*(const DN<N>& a, const DN<N>& b) {
+  DN<N> r;
+  r.v = a.v * b.v;
+#pragma unroll
+  for (int k = 0; k < N; ++k) r.d[k] = a.d[k] * b.v + a.v * b.d[k];
+  return r;
+}
+template <int N> __device__ __forceinline__ DN<N> operator/(const DN<N>& a, const DN<N>& b) {
+  DN<N> r;
+  const double ib = 1.0 / b.v;
+  r.v = a.v * ib;
+#pragma unroll
+  for (int k = 0; k < N; ++k) r.d[k] = (a.d[k] - r.v * b.d[k]) * ib;
+  return r;
+}
+template <int N> __device__ __forceinline__ DN<N> operator+(const DN<N>& a, double b) {
+  DN<N> r = a;
+  r.v += b;
+  return r;
+}
+template <int N> __device__ __forceinline__ DN<N> operator+(double a, const DN<N>& b) { return b + a; }
+template <int N> __device__ __forceinline__ DN<N> operator-(const DN<N>& a, double b) {
+  DN<N> r = a;
+  r.v -= b;
+  return r;
+}
+template <int N> __device__ __forceinline__ DN<N> operator-(double a, const DN<N>& b) {
+  DN<N> r;
+  r.v = a - b.v;
+#pragma unroll
+  for (int k = 0; k < N; ++k) r.d[k] = -b.d[k];
+  return r;
+}
+template <int N> __device__ __forceinline__ DN<N> operator*(const DN<N>& a, double b) {
+  DN<N> r;
+  r.v = a.v * b;
+#pragma unroll
+  for (int k = 0; k < N; ++k) r.d[k] = a.d[k] * b;
+  return r;
+}
+template <int N> __device__ __forceinline__ DN<N> operator*(double a, const DN<N>& b) { return b * a; }
+template <int N> __device__ __forceinline__ DN<N> operator/(const DN<N>& a, double b) { return a * (1.0 / b); }
+template <int N> __device__ __forceinline__ DN<N> operator/(double a, const DN<N>& b) {
+  DN<N> r;
+  const double ib = 1.0 / b.v;
+  r.v = a * ib;
+  const double s = -r.v * ib;
+#pragma unroll
+  for (int k = 0; k < N; ++k) r.d[k] = s * b.d[k];
+  return r;
+}
+template <int N> __device__ __forceinline__ bool operator<(const DN<N>& a, const DN<N>& b) { return a.v < b.v; }
+template <int N> __device__ __forceinline__ bool operator>(const DN<N>& a, const DN<N>& b) { return a.v > b.v; }
+template <int N> __device__ __forceinline__ bool operator<=(const DN<N>& a, const DN<N>& b) { return a.v <= b.v; }
+template <int N> __device__ __forceinline__ bool operator==(const DN<N>& a, const DN<N>& b) { return a.v == b.v; }
+template <int N> __device__ __forceinline__ DN<N> sqrt_r(const DN<N>& a) {
+  DN<N> r;
+  r.v = sqrt(a.v);
+  const double h = 0.5 / r.v;
+#pragma unroll
+  for (int k = 0; k < N; ++k) r.d[k] = a.d[k] * h;
+  return r;
+}
+
+// ---------------------------------------------------------------- reconstruction gradients
+
+// WENO5 value at the right face of c in (a, b, c, d, e) and its gradient with
+// respect to (a, b, c, d, e).  The weights are differentiated in their
+// un-normalised product form (JS: d_k prod_{j != k} (eps + beta_j)^2; Z:
+// d_k (e_k^p + tau^p) prod_{j != k} e_j^p, e = beta + eps, tau = |beta_0 - beta_2|),
+// which normalises to the forward kernel's weights.
+template <bool ZW>
+__device__ __forceinline__ double weno5_grad(const double* s, double eps, int zp, double g[5]) {
+  const double a = s[0], b = s[1], c = s[2], d = s[3], e = s[4];
+  const double q[3] = {2 * a - 7 * b + 11 * c, -b + 5 * c + 2 * d, 2 * c + 5 * d - e};
+  const double X0 = a - 2 * b + c, Y0 = a - 4 * b + 3 * c;
+  const double X1 = b - 2 * c + d, Y1 = b - d;
+  const double X2 = c - 2 * d + e, Y2 = 3 * c - 4 * d + e;
+  const double be[3] = {13.0 / 12.0 * X0 * X0 + 0.25 * Y0 * Y0, 13.0 / 12.0 * X1 * X1 + 0.25 * Y1 * Y1,
+                        13.0 / 12.0 * X2 * X2 + 0.25 * Y2 * Y2};
+  const double dk[3] = {0.1, 0.6, 0.3};
+  double w[3], dw[3][3];  // dw[k][m] = d w_k / d beta_m
+  if (!ZW) {
+    double t[3], tp[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      t[k] = (eps + be[k]) * (eps + be[k]);
+      tp[k] = 2.0 * (eps + be[k]);
+    }
+    w[0] = dk[0] * t[1] * t[2];
+    w[1] = dk[1] * t[0] * t[2];
+    w[2] = dk[2] * t[0] * t[1];
+    dw[0][0] = 0.0;                 dw[0][1] = dk[0] * tp[1] * t[2]; dw[0][2] = dk[0] * t[1] * tp[2];
+    dw[1][0] = dk[1] * tp[0] * t[2]; dw[1][1] = 0.0;                 dw[1][2] = dk[1] * t[0] * tp[2];
+    dw[2][0] = dk[2] * tp[0] * t[1]; dw[2][1] = dk[2] * t[0] * tp[1]; dw[2][2] = 0.0;
+  } else {
+    const double tau = fabs(be[0] - be[2]);
+    const double sg = (be[0] > be[2]) ? 1.0 : ((be[0] < be[2]) ? -1.0 : 0.0);
+    const double dtau[3] = {sg, 0.0, -sg};
+    double ep[3], epd[3];  // e^p and d(e^p)/de
+    double e_[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      e_[k] = be[k] + eps;
+      ep[k] = (zp == 2) ? e_[k] * e_[k] : e_[k];
+      epd[k] = (zp == 2) ? 2.0 * e_[k] : 1.0;
+    }
+    const double tp = (zp == 2) ? tau * tau : tau;
+    const double tpd = (zp == 2) ? 2.0 * tau : 1.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const int j = (k + 1) % 3, l = (k + 2) % 3;
+      const double f = ep[k] + tp;
+      const double gk = ep[j] * ep[l];
+      w[k] = dk[k] * f * gk;
+#pragma unroll
+      for (int m = 0; m < 3; ++m) {
+        double df = tpd * dtau[m] + (m == k ? epd[k] : 0.0);
+        double dg = (m == j) ? epd[j] * ep[l] : ((m == l) ? ep[j] * epd[l] : 0.0);
+        dw[k][m] = dk[k] * (df * gk + f * dg);
+      }
+    }
+  }
+  const double W = w[0] + w[1] + w[2];
+  const double i6W = 1.0 / (6.0 * W);
+  const double qv = (w[0] * q[0] + w[1] * q[1] + w[2] * q[2]) * i6W;
+  // d qv / d w_k and d qv / d beta_m
+  double cw[3], cb[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) cw[k] = (q[k] - 6.0 * qv) * i6W;
+#pragma unroll
+  for (int m = 0; m < 3; ++m) cb[m] = cw[0] * dw[0][m] + cw[1] * dw[1][m] + cw[2] * dw[2][m];
+  const double o0 = w[0] * i6W, o1 = w[1] * i6W, o2 = w[2] * i6W;
+  // candidates: q0 = (2, -7, 11, 0, 0), q1 = (0, -1, 5, 2, 0), q2 = (0, 0, 2, 5, -1)
+  g[0] = 2 * o0;
+  g[1] = -7 * o0 - o1;
+  g[2] = 11 * o0 + 5 * o1 + 2 * o2;
+  g[3] = 2 * o1 + 5 * o2;
+  g[4] = -o2;
+  // smoothness indicators
+  const double k13 = 13.0 / 6.0;
+  g[0] += cb[0] * (k13 * X0 + 0.5 * Y0);
+  g[1] += cb[0] * (-2 * k13 * X0 - 2.0 * Y0) + cb[1] * (k13 * X1 + 0.5 * Y1);
+  g[2] += cb[0] * (k13 * X0 + 1.5 * Y0) + cb[1] * (-2 * k13 * X1) + cb[2] * (k13 * X2 + 1.5 * Y2);
+  g[3] += cb[1] * (k13 * X1 - 0.5 * Y1) + cb[2] * (-2 * k13 * X2 - 2.0 * Y2);
+  g[4] += cb[2] * (k13 * X2 + 0.5 * Y2);
+  return qv;
+}
+
+// minmod left state s[2] + mm(s[2]-s[1], s[3]-s[2]) / 2 and its gradient w.r.t. s[1..3]
+__device__ __forceinline__ double minmod_grad(double s1, double s2, double s3, double g[3]) {
+  const double x = s2 - s1, y = s3 - s2;
+  if (x * y <= 0.0) {
+    g[0] = 0.0; g[1] = 1.0; g[2] = 0.0;
+    return s2;
+  }
+  if (fabs(x) < fabs(y)) {
+    g[0] = -0.5; g[1] = 1.5; g[2] = 0.0;
+    return s2 + 0.5 * x;
+  }
+  g[0] = 0.0; g[1] = 0.5; g[2] = 0.5;
+  return s2 + 0.5 * y;
+}
+
+}  // namespace gk
+
+namespace gk {
+
+// Reverse pass of one face side (FP64): given the adjoints of the side's
+// conserved variables Ub, direction-D fluxes Fb and speed bounds lpb, lmb,
+// accumulate the adjoint of its 8 primitives into Pb.  The forward
+// intermediates are recomputed in the same order as side_v2 / side_rest /
+// side_speeds / side_cons_flux, then every statement is reversed.
+template <int D>
+__device__ __forceinline__ void side_vjp(const FaceMetric<double>& m, const double* P, double gam, double gm1,
+                                         const double* Ub, const double* Fb, double lpb, double lmb, double* Pb) {
+  const double* g = m.g;
+  const double rho = P[0], eps = P[4];
+  const double v[3] = {P[1], P[2], P[3]};
+  const double B[3] = {P[5], P[6], P[7]};
+  double vl[3], Bl[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    vl[i] = g[sidx(i, 0)] * v[0] + g[sidx(i, 1)] * v[1] + g[sidx(i, 2)] * v[2];
+    Bl[i] = g[sidx(i, 0)] * B[0] + g[sidx(i, 1)] * B[1] + g[sidx(i, 2)] * B[2];
+  }
+  const double v2 = vl[0] * v[0] + vl[1] * v[1] + vl[2] * v[2];
+  const double om = 1.0 - v2;
+  const double iW = sqrt(om);
+  const double W = 1.0 / iW;
+  const double B2 = Bl[0] * B[0] + Bl[1] * B[1] + Bl[2] * B[2];
+  const double Bv = Bl[0] * v[0] + Bl[1] * v[1] + Bl[2] * v[2];
+  const double ab0 = W * Bv;
+  const double iW2 = iW * iW;
+  const double b2 = (B2 + ab0 * ab0) * iW2;
+  const double p = gm1 * rho * eps;
+  const double rhoh = rho * (1.0 + eps) + p;
+  // speeds
+  const double cs2 = gam * p / rhoh;
+  const double qq = rhoh + b2;
+  const double ca2 = b2 / qq;
+  const double cf2 = cs2 + ca2 - cs2 * ca2;
+  const double vd = v[D];
+  const double den = 1.0 - v2 * cf2;
+  const double X = m.gdd * den - vd * vd * (1.0 - cf2);
+  const double disc = om * X;
+  const double dc = disc < 0.0 ? 0.0 : disc;
+  const double root = sqrt(cf2 * dc);
+  const double base = vd * (1.0 - cf2);
+  const double ad = m.alpha / den;
+  // cons / flux
+  const double W2 = W * W;
+  const double rhohs = rhoh + b2;
+  const double Ps = p + 0.5 * b2;
+  const double sg = m.sqrtg, al = m.alpha;
+  double bl[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) bl[i] = Bl[i] * iW + ab0 * vl[i];
+  double U[8];
+  U[0] = sg * rho * W;
+#pragma unroll
+  for (int j = 0; j < 3; ++j) U[1 + j] = sg * (rhohs * W2 * vl[j] - ab0 * bl[j]);
+  U[4] = sg * (rhohs * W2 - Ps - ab0 * ab0) - U[0];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) U[5 + k] = sg * B[k];
+  const double ia = 1.0 / al;
+  double vt[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) vt[i] = v[i] - m.beta[i] * ia;
+  const double BnW = U[5 + D] * iW;
+
+  // ---- reverse ----
+  double Ubar[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) Ubar[q] = Ub[q];
+  double vtb[3] = {0.0, 0.0, 0.0}, vb_[3] = {0.0, 0.0, 0.0}, Bb_[3] = {0.0, 0.0, 0.0};
+  double Psb = 0.0, ab0b = 0.0, BnWb = 0.0, blb[3] = {0.0, 0.0, 0.0};
+  // F_{5+k}, k != D
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    if (k == D) continue;
+    const double f = Fb[5 + k] * al;
+    Ubar[5 + k] += f * vt[D];
+    vtb[D] += f * U[5 + k];
+    Ubar[5 + D] -= f * vt[k];
+    vtb[k] -= f * U[5 + D];
+  }
+  {  // F4
+    const double f = Fb[4] * al;
+    Ubar[4] += f * vt[D];
+    vtb[D] += f * U[4];
+    Psb += f * sg * v[D];
+    vb_[D] += f * sg * Ps;
+    ab0b -= f * BnW;
+    BnWb -= f * ab0;
+  }
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {  // F_{1+j}
+    const double f = Fb[1 + j] * al;
+    Ubar[1 + j] += f * vt[D];
+    vtb[D] += f * U[1 + j];
+    blb[j] -= f * BnW;
+    BnWb -= f * bl[j];
+    if (j == D) Psb += f * sg;
+  }
+  {  // F0
+    const double f = Fb[0] * al;
+    Ubar[0] += f * vt[D];
+    vtb[D] += f * U[0];
+  }
+  double iWb = 0.0;
+  Ubar[5 + D] += BnWb * iW;
+  iWb += BnWb * U[5 + D];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) vb_[i] += vtb[i];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) Bb_[k] += Ubar[5 + k] * sg;
+  double rhohsb = 0.0, W2b = 0.0, Wb = 0.0, rhob = 0.0, vlb[3] = {0.0, 0.0, 0.0};
+  {  // U4
+    const double f = Ubar[4] * sg;
+    rhohsb += f * W2;
+    W2b += f * rhohs;
+    Psb -= f;
+    ab0b -= f * 2.0 * ab0;
+    Ubar[0] -= Ubar[4];
+  }
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {  // U_{1+j}
+    const double f = Ubar[1 + j] * sg;
+    rhohsb += f * W2 * vl[j];
+    W2b += f * rhohs * vl[j];
+    vlb[j] += f * rhohs * W2;
+    ab0b -= f * bl[j];
+    blb[j] -= f * ab0;
+  }
+  rhob += Ubar[0] * sg * W;
+  Wb += Ubar[0] * sg * rho;
+  double Blb[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {  // bl_i = Bl_i iW + ab0 vl_i
+    Blb[i] = blb[i] * iW;
+    iWb += blb[i] * Bl[i];
+    ab0b += blb[i] * vl[i];
+    vlb[i] += blb[i] * ab0;
+  }
+  double pb = Psb, b2b = 0.5 * Psb;
+  double rhohb = rhohsb;
+  b2b += rhohsb;
+  Wb += 2.0 * W * W2b;
+  // speeds
+  const double lsum = lpb * (base + root) + lmb * (base - root);
+  const double adb = lsum;
+  const double baseb = (lpb + lmb) * ad;
+  const double rootb = (lpb - lmb) * ad;
+  double denb = -adb * ad / den;
+  double vdb = baseb * (1.0 - cf2);
+  double cf2b = -baseb * vd;
+  double dcb = 0.0;
+  if (root > 0.0) {
+    const double r2b = rootb / (2.0 * root);
+    cf2b += r2b * dc;
+    dcb = r2b * cf2;
+  }
+  const double discb = disc < 0.0 ? 0.0 : dcb;
+  double omb = discb * X;
+  const double Xb = discb * om;
+  denb += Xb * m.gdd;
+  vdb -= Xb * 2.0 * vd * (1.0 - cf2);
+  cf2b += Xb * vd * vd;
+  double v2b = -denb * cf2;
+  cf2b -= denb * v2;
+  vb_[D] += vdb;
+  const double cs2b = cf2b * (1.0 - ca2);
+  const double ca2b = cf2b * (1.0 - cs2);
+  b2b += ca2b * (1.0 - ca2) / qq;
+  rhohb -= ca2b * ca2 / qq;
+  pb += cs2b * gam / rhoh;
+  rhohb -= cs2b * cs2 / rhoh;
+  // state
+  rhob += rhohb * (1.0 + eps);
+  double epsb = rhohb * rho;
+  pb += rhohb;
+  rhob += pb * gm1 * eps;
+  epsb += pb * gm1 * rho;
+  const double B2b = b2b * iW2;
+  ab0b += b2b * iW2 * 2.0 * ab0;
+  const double iW2b = b2b * (B2 + ab0 * ab0);
+  iWb += 2.0 * iW * iW2b;
+  Wb += ab0b * Bv;
+  const double Bvb = ab0b * W;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    Blb[i] += Bvb * v[i] + B2b * B[i];
+    vb_[i] += Bvb * Bl[i];
+    Bb_[i] += B2b * Bl[i];
+  }
+  iWb += -Wb * W * W;
+  omb += iWb / (2.0 * iW);
+  v2b -= omb;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    vlb[i] += v2b * v[i];
+    vb_[i] += v2b * vl[i];
+  }
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    Bb_[j] += g[sidx(0, j)] * Blb[0] + g[sidx(1, j)] * Blb[1] + g[sidx(2, j)] * Blb[2];
+    vb_[j] += g[sidx(0, j)] * vlb[0] + g[sidx(1, j)] * vlb[1] + g[sidx(2, j)] * vlb[2];
+  }
+  Pb[0] += rhob;
+  Pb[1] += vb_[0];
+  Pb[2] += vb_[1];
+  Pb[3] += vb_[2];
+  Pb[4] += epsb;
+  Pb[5] += Bb_[0];
+  Pb[6] += Bb_[1];
+  Pb[7] += Bb_[2];
+}
+
+}  // namespace gk

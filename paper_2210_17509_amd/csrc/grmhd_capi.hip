@@ -22,6 +22,7 @@
 #include <vector>
 
 #include "grmhd.h"
+#include "grmhd_adjoint.h"
 #include "grmhd_device.h"
 
 using namespace gk;
@@ -56,6 +57,7 @@ struct CellArgs {
   Table tab;
   double* U;
   double* P;
+  int32_t write_u;  // 0: U is read only (atmosphere resets are not written back)
   double* ckpt;  // nullable copy of U after con2prim
   int32_t* status;
   unsigned long long* n_fail;
@@ -245,10 +247,12 @@ __global__ __launch_bounds__(256) void k_stage(StageArgs a) {
     const int vb = ((k + ng) * (bx.VXY / bx.VX) + (j + ng)) * bx.VX + (i + ng);
     CentreMetric cm;
     centre_metric<SHIFT, true>(alb, beb, gab, a.vs, vb, bx.VX, bx.VXY, cm);
+    MetricDeriv md;
+    metric_deriv<SHIFT>(alb, beb, gab, a.vs, vb, bx.VX, bx.VXY, bx.inv_dx, md);
     double P[8], S[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) P[q] = Pb[q * a.cs + c];
-    sources<SHIFT>(alb, beb, gab, a.vs, vb, bx.VX, bx.VXY, bx.inv_dx, cm, P, a.ph.gam, S);
+    sources_T<SHIFT>(cm, md, P, a.ph.gam, S);
     const int64_t cc = bx.cell_off + c;
     if (a.mode == 0) {
 #pragma unroll
@@ -300,7 +304,7 @@ __global__ __launch_bounds__(C2P_BLOCK) void k_con2prim(CellArgs a) {
     const int st = c2p_cell(cm.g, cm.gi, cm.sqrtg, a.ph, U, P);
 #pragma unroll
     for (int q = 0; q < 8; ++q) a.P[q * a.cs + cc] = P[q];
-    if (st != C2P_OK && st != C2P_FALLBACK) {
+    if (a.write_u && st != C2P_OK && st != C2P_FALLBACK) {
 #pragma unroll
       for (int q = 0; q < 8; ++q) a.U[q * a.cs + cc] = U[q];
     }
@@ -332,6 +336,339 @@ __global__ __launch_bounds__(C2P_BLOCK) void k_prim2con(Table tab, const double*
   p2c_cell(cm.g, cm.sqrtg, gm1, p, u);
 #pragma unroll
   for (int q = 0; q < 8; ++q) U[q * cs + cc] = u[q];
+}
+
+
+// ---------------------------------------------------------------- adjoint kernels
+
+struct AdjArgs {
+  Table tab;
+  const double* __restrict__ P;   // primitives of the stage state
+  const double* __restrict__ V;   // vector the Jacobian transpose is applied to
+  double* __restrict__ Pbar;      // accumulated adjoint of the primitives
+  const double* __restrict__ alpha;
+  const double* __restrict__ beta;
+  const double* __restrict__ gamma;
+  int64_t cs, vs;
+  KPhys ph;
+};
+
+// Face VJP: Fbar = (v_c - v_{c-1}) / dx_D, then the reverse of HLLE, of the two
+// side states and of the reconstruction, scattered onto the stencil cells of
+// the face (ghost cells map onto the interior cells they copy).
+template <int D, int RECON, bool SHIFT>
+__global__ __launch_bounds__(256) void k_adj_face(AdjArgs a) {
+  const int nb = a.tab.nbox;
+  const int32_t* pre = a.tab.face_prefix + D * (nb + 1);
+  const int b = find_box(pre, nb, blockIdx.x);
+  const KBox& bx = a.tab.box[b];
+  const int nfx = bx.n[0] + (D == 0), nfy = bx.n[1] + (D == 1), nfz = bx.n[2] + (D == 2);
+  const int lin = (blockIdx.x - pre[b]) * FACE_BLOCK + threadIdx.x;
+  if (lin >= nfx * nfy * nfz) return;
+  const int i = lin % nfx;
+  const int r = lin / nfx;
+  const int j = r % nfy;
+  const int k = r / nfy;
+  const int ng = bx.ng;
+  const int c = (D == 0) ? i : (D == 1 ? j : k);
+  const int nD = bx.n[D];
+  const int sD = (D == 0) ? 1 : (D == 1 ? bx.NX : bx.NXY);
+  const int base = (D == 0)   ? ((k + ng) * (bx.NXY / bx.NX) + (j + ng)) * bx.NX + ng
+                   : (D == 1) ? (k + ng) * bx.NXY + ng * bx.NX + (i + ng)
+                              : ng * bx.NXY + (j + ng) * bx.NX + (i + ng);
+  int idx[6];
+#pragma unroll
+  for (int o = 0; o < 6; ++o) {
+    const int m = c + o - 3;
+    const int mm = (m < 0) ? bx.mlo[D][(m + 3) < 0 ? 0 : m + 3] : (m >= nD ? bx.mhi[D][(m - nD) > 2 ? 2 : m - nD] : m);
+    idx[o] = base + mm * sD;
+  }
+  const double* __restrict__ Pb = a.P + bx.cell_off;
+  const double* __restrict__ Vb = a.V + bx.cell_off;
+  double* __restrict__ Gb = a.Pbar + bx.cell_off;
+  // adjoint of the face flux
+  double Fb[8];
+  bool any = false;
+  const double id = bx.inv_dx[D];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const double vr = (c < nD) ? Vb[q * a.cs + idx[3]] : 0.0;
+    const double vl = (c >= 1) ? Vb[q * a.cs + idx[2]] : 0.0;
+    Fb[q] = (vr - vl) * id;
+    any = any || (Fb[q] != 0.0);
+  }
+  if (!any) return;
+  // forward reconstruction values
+  double PL[8], PR[8];
+  const double eps = (RECON == GRMHD_RECON_WENOZ) ? a.ph.wenoz_eps : a.ph.weno_eps;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const double* __restrict__ f = Pb + q * a.cs;
+    double s[6];
+#pragma unroll
+    for (int o = 0; o < 6; ++o) s[o] = (RECON == GRMHD_RECON_MINMOD && (o == 0 || o == 5)) ? 0.0 : f[idx[o]];
+    if (RECON == GRMHD_RECON_MINMOD) {
+      PL[q] = s[2] + 0.5 * minmod(s[2] - s[1], s[3] - s[2]);
+      PR[q] = s[3] - 0.5 * minmod(s[3] - s[2], s[4] - s[3]);
+    } else {
+      PL[q] = weno5<RECON == GRMHD_RECON_WENOZ>(s[0], s[1], s[2], s[3], s[4], eps, a.ph.wenoz_p);
+      PR[q] = weno5<RECON == GRMHD_RECON_WENOZ>(s[5], s[4], s[3], s[2], s[1], eps, a.ph.wenoz_p);
+    }
+  }
+  const int vb = ((k + ng) * (bx.VXY / bx.VX) + (j + ng)) * bx.VX + (i + ng);
+  constexpr int A = (D + 1) % 3, B = (D + 2) % 3;
+  const int sa = (A == 0) ? 1 : (A == 1 ? bx.VX : bx.VXY);
+  const int sb = (B == 0) ? 1 : (B == 1 ? bx.VX : bx.VXY);
+  FaceMetric<double> m;
+  face_metric<D, SHIFT, double>(a.alpha + bx.vert_off, SHIFT ? a.beta + bx.vert_off : nullptr,
+                                a.gamma + bx.vert_off, a.vs, vb, sa, sb, m);
+  SideState<double> sL, sR;
+  side_v2(m, PL, sL);
+  side_v2(m, PR, sR);
+  const bool fbL = !side_ok(PL, sL.v2), fbR = !side_ok(PR, sR.v2);
+  if (fbL) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) PL[q] = Pb[q * a.cs + idx[2]];
+    side_v2(m, PL, sL);
+  }
+  if (fbR) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) PR[q] = Pb[q * a.cs + idx[3]];
+    side_v2(m, PR, sR);
+  }
+  const double gam = a.ph.gam, gm1 = a.ph.gm1;
+  side_rest(m, PL, gm1, sL);
+  side_rest(m, PR, gm1, sR);
+  double lpL, lmL, lpR, lmR;
+  side_speeds<D>(m, PL, sL, gam, lpL, lmL);
+  side_speeds<D>(m, PR, sR, gam, lpR, lmR);
+  // forward branch choices of xi+ = max(0, max(lpL, lpR)), xi- = min(0, min(lmL, lmR))
+  const double mp = (lpL < lpR) ? lpR : lpL;
+  const int mpi = (lpL < lpR) ? 2 : 1;
+  const double mn = (lmR < lmL) ? lmR : lmL;
+  const int mni = (lmR < lmL) ? 2 : 1;
+  const double xip = (0.0 < mp) ? mp : 0.0;
+  const int ip = (0.0 < mp) ? mpi : 0;
+  const double xim = (mn < 0.0) ? mn : 0.0;
+  const int im = (mn < 0.0) ? mni : 0;
+  const double den = xip - xim;
+  double UL[8], FL[8], UR[8], FR[8];
+  side_cons_flux<D>(m, PL, sL, UL, FL);
+  side_cons_flux<D>(m, PR, sR, UR, FR);
+  double gFL[8], gFR[8], gUL[8], gUR[8];
+  double xbp = 0.0, xbm = 0.0;
+  if (den > 0.0) {
+    const double idn = 1.0 / den;
+    const double xx = xip * xim;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const double du = UR[q] - UL[q];
+      const double Fs = (xip * FL[q] - xim * FR[q] + xx * du) * idn;
+      gFL[q] = Fb[q] * xip * idn;
+      gFR[q] = -Fb[q] * xim * idn;
+      gUL[q] = -Fb[q] * xx * idn;
+      gUR[q] = Fb[q] * xx * idn;
+      xbp += Fb[q] * (FL[q] + xim * du - Fs) * idn;
+      xbm += Fb[q] * (-FR[q] + xip * du + Fs) * idn;
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      gFL[q] = gFR[q] = 0.5 * Fb[q];
+      gUL[q] = gUR[q] = 0.0;
+    }
+  }
+  double qbL[8], qbR[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) qbL[q] = qbR[q] = 0.0;
+  side_vjp<D>(m, PL, gam, gm1, gUL, gFL, ip == 1 ? xbp : 0.0, im == 1 ? xbm : 0.0, qbL);
+  side_vjp<D>(m, PR, gam, gm1, gUR, gFR, ip == 2 ? xbp : 0.0, im == 2 ? xbm : 0.0, qbR);
+  // reverse of the reconstruction, scattered onto the stencil cells
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const double* __restrict__ f = Pb + q * a.cs;
+    double sb[6] = {0, 0, 0, 0, 0, 0};
+    if (RECON == GRMHD_RECON_MINMOD) {
+      const double s1 = f[idx[1]], s2 = f[idx[2]], s3 = f[idx[3]], s4 = f[idx[4]];
+      double g3[3];
+      if (fbL) sb[2] += qbL[q];
+      else {
+        minmod_grad(s1, s2, s3, g3);
+        sb[1] += qbL[q] * g3[0]; sb[2] += qbL[q] * g3[1]; sb[3] += qbL[q] * g3[2];
+      }
+      if (fbR) sb[3] += qbR[q];
+      else {
+        minmod_grad(s4, s3, s2, g3);
+        sb[4] += qbR[q] * g3[0]; sb[3] += qbR[q] * g3[1]; sb[2] += qbR[q] * g3[2];
+      }
+    } else {
+      double s[6];
+#pragma unroll
+      for (int o = 0; o < 6; ++o) s[o] = f[idx[o]];
+      double g5[5];
+      if (fbL) sb[2] += qbL[q];
+      else {
+        weno5_grad<RECON == GRMHD_RECON_WENOZ>(s, eps, a.ph.wenoz_p, g5);
+#pragma unroll
+        for (int o = 0; o < 5; ++o) sb[o] += qbL[q] * g5[o];
+      }
+      if (fbR) sb[3] += qbR[q];
+      else {
+        const double sr[5] = {s[5], s[4], s[3], s[2], s[1]};
+        weno5_grad<RECON == GRMHD_RECON_WENOZ>(sr, eps, a.ph.wenoz_p, g5);
+#pragma unroll
+        for (int o = 0; o < 5; ++o) sb[5 - o] += qbR[q] * g5[o];
+      }
+    }
+#pragma unroll
+    for (int o = 0; o < 6; ++o)
+      if (sb[o] != 0.0) unsafeAtomicAdd(Gb + q * a.cs + idx[o], sb[o]);
+  }
+}
+
+// Solve A^T x = y for the 8x8 Jacobian A = dU/dP of Eqs. (p2c1)-(p2c4); A has
+// the block form [[A11, A12], [0, sqrt(g) I3]] (U_B = sqrt(g) B).
+__device__ __forceinline__ void solve_dUdP_T(const DN<8>* U, double sqrtg, const double* y, double* x) {
+  double M[5][6];  // A11^T | rhs
+#pragma unroll
+  for (int r = 0; r < 5; ++r) {
+#pragma unroll
+    for (int cc = 0; cc < 5; ++cc) M[r][cc] = U[cc].d[r];
+    M[r][5] = y[r];
+  }
+  // Gaussian elimination with partial pivoting
+#pragma unroll
+  for (int col = 0; col < 5; ++col) {
+    int piv = col;
+    double best = fabs(M[col][col]);
+#pragma unroll
+    for (int r = col + 1; r < 5; ++r)
+      if (fabs(M[r][col]) > best) { best = fabs(M[r][col]); piv = r; }
+#pragma unroll
+    for (int r = col + 1; r < 5; ++r) {  // row swap with static indices only
+      const bool sw = (r == piv);
+#pragma unroll
+      for (int cc = 0; cc < 6; ++cc) {
+        const double t = M[col][cc];
+        M[col][cc] = sw ? M[r][cc] : t;
+        M[r][cc] = sw ? t : M[r][cc];
+      }
+    }
+    const double ip = 1.0 / M[col][col];
+#pragma unroll
+    for (int r = col + 1; r < 5; ++r) {
+      const double f = M[r][col] * ip;
+#pragma unroll
+      for (int cc = col; cc < 6; ++cc) M[r][cc] -= f * M[col][cc];
+    }
+  }
+#pragma unroll
+  for (int r = 4; r >= 0; --r) {
+    double t = M[r][5];
+#pragma unroll
+    for (int cc = r + 1; cc < 5; ++cc) t -= M[r][cc] * x[cc];
+    x[r] = t / M[r][r];
+  }
+  // rows of A^T for the field components: sum_{q<5} A[q][5+k] x_q + sqrt(g) x_{5+k} = y_{5+k}
+  const double is = 1.0 / sqrtg;
+#pragma unroll
+  for (int kk = 0; kk < 3; ++kk) {
+    double t = y[5 + kk];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) t -= U[q].d[5 + kk] * x[q];
+    x[5 + kk] = t * is;
+  }
+}
+
+struct AdjCellArgs {
+  Table tab;
+  const double* __restrict__ P;
+  double* V;                      // in: v = adjoint of U_{s+1}; out (stage > 0): adjoint of U_s
+  double* Gn;                     // accumulated adjoint of U^n
+  const double* __restrict__ Pbar;
+  const double* __restrict__ alpha;
+  const double* __restrict__ beta;
+  const double* __restrict__ gamma;
+  int64_t cs, vs;
+  KPhys ph;
+  double cstage, dt;
+  int32_t first_stage;
+  int32_t mode;  // 0: RK stage adjoint; 1: con2prim adjoint only (V = gP in, Gn = gU out)
+};
+
+// Cell part of the stage adjoint: source VJP, con2prim through the implicit-
+// function theorem, and the transposed stage combine
+// U_{s+1} = (1 - c) U^n + c U_s + c dt L(U_s).
+template <bool SHIFT>
+__global__ __launch_bounds__(C2P_BLOCK) void k_adj_cell(AdjCellArgs a) {
+  int b, c, vb;
+  if (!cell_of(a.tab, blockIdx.x, threadIdx.x, b, c, vb)) return;
+  const KBox& bx = a.tab.box[b];
+  const int64_t cc = bx.cell_off + c;
+  CentreMetric cm;
+  centre_metric<SHIFT, true>(a.alpha + bx.vert_off, SHIFT ? a.beta + bx.vert_off : nullptr, a.gamma + bx.vert_off,
+                             a.vs, vb, bx.VX, bx.VXY, cm);
+  double P[8], v[8], pb[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    P[q] = a.P[q * a.cs + cc];
+    v[q] = a.V[q * a.cs + cc];
+    pb[q] = (a.mode == 0) ? a.Pbar[q * a.cs + cc] : v[q];
+  }
+  DN<8> Pd[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    Pd[q] = DN<8>(P[q]);
+    Pd[q].d[q] = 1.0;
+  }
+  if (a.mode == 0) {
+    MetricDeriv md;
+    metric_deriv<SHIFT>(a.alpha + bx.vert_off, SHIFT ? a.beta + bx.vert_off : nullptr, a.gamma + bx.vert_off, a.vs,
+                        vb, bx.VX, bx.VXY, bx.inv_dx, md);
+    DN<8> S[8];
+    sources_T<SHIFT>(cm, md, Pd, a.ph.gam, S);
+#pragma unroll
+    for (int q = 1; q < 5; ++q)
+#pragma unroll
+      for (int kk = 0; kk < 8; ++kk) pb[kk] += v[q] * S[q].d[kk];
+  }
+  DN<8> U[8];
+  p2c_cell(cm.g, cm.sqrtg, a.ph.gm1, Pd, U);
+  double w[8];
+  solve_dUdP_T(U, cm.sqrtg, pb, w);
+  if (a.mode == 1) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) a.Gn[q * a.cs + cc] = w[q];
+    return;
+  }
+  const double cs = a.cstage;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const double gs = cs * (v[q] + a.dt * w[q]);
+    double gn = a.Gn[q * a.cs + cc] + (1.0 - cs) * v[q];
+    if (a.first_stage) gn += gs;
+    else a.V[q * a.cs + cc] = gs;
+    a.Gn[q * a.cs + cc] = gn;
+  }
+}
+
+// Fill the interior cells of 8 pooled fields with a value.
+__global__ __launch_bounds__(C2P_BLOCK) void k_fill(Table tab, double* X, int64_t cs, double val) {
+  int b, c, vb;
+  if (!cell_of(tab, blockIdx.x, threadIdx.x, b, c, vb)) return;
+  const int64_t cc = tab.box[b].cell_off + c;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) X[q * cs + cc] = val;
+}
+
+// Copy the interior cells of 8 pooled fields.
+__global__ __launch_bounds__(C2P_BLOCK) void k_copy(Table tab, const double* __restrict__ X, double* __restrict__ Y,
+                                                     int64_t cs) {
+  int b, c, vb;
+  if (!cell_of(tab, blockIdx.x, threadIdx.x, b, c, vb)) return;
+  const int64_t cc = tab.box[b].cell_off + c;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) Y[q * cs + cc] = X[q * cs + cc];
 }
 
 // ---------------------------------------------------------------- host side
@@ -396,6 +733,7 @@ struct Prepared {
   int32_t nbox;
   int64_t c2p_blocks;
   int64_t tiles[NTILE];
+  int64_t face_blocks[3];
 };
 std::mutex g_mu;
 std::unordered_map<const void*, Prepared> g_prepared;
@@ -427,7 +765,7 @@ int invalid(const char* why) {
 }
 
 size_t table_bytes(int32_t nbox) {
-  return sizeof(TableHeader) + sizeof(KBox) * (size_t)nbox + sizeof(int32_t) * (size_t)(nbox + 1) * (1 + NTILE);
+  return sizeof(TableHeader) + sizeof(KBox) * (size_t)nbox + sizeof(int32_t) * (size_t)(nbox + 1) * (1 + NTILE + 3);
 }
 
 int periodic_map(int m, int n) { return ((m % n) + n) % n; }
@@ -521,6 +859,7 @@ Table make_table(const grmhd_domain* dom) {
   t.box = reinterpret_cast<const KBox*>(base + sizeof(TableHeader));
   t.c2p_prefix = reinterpret_cast<const int32_t*>(base + sizeof(TableHeader) + sizeof(KBox) * (size_t)dom->nbox);
   t.tile_prefix = t.c2p_prefix + (dom->nbox + 1);
+  t.face_prefix = t.tile_prefix + NTILE * (dom->nbox + 1);
   t.nbox = dom->nbox;
   return t;
 }
@@ -575,6 +914,7 @@ hipError_t launch_c2p(const grmhd_domain* dom, const Prepared& pr, const KPhys& 
   a.tab = make_table(dom);
   a.U = U;
   a.P = P;
+  a.write_u = 1;
   a.ckpt = ckpt;
   a.status = status;
   a.n_fail = reinterpret_cast<unsigned long long*>(n_fail);
@@ -608,6 +948,35 @@ StageArgs stage_args(const grmhd_domain* dom, const grmhd_params* par, const KPh
   return a;
 }
 
+
+template <int RECON, bool SHIFT>
+hipError_t launch_adj_faces(const AdjArgs& a, const Prepared& pr, hipStream_t s) {
+  if (pr.face_blocks[0] > 0) hipLaunchKernelGGL((k_adj_face<0, RECON, SHIFT>), dim3((unsigned)pr.face_blocks[0]), dim3(FACE_BLOCK), 0, s, a);
+  if (pr.face_blocks[1] > 0) hipLaunchKernelGGL((k_adj_face<1, RECON, SHIFT>), dim3((unsigned)pr.face_blocks[1]), dim3(FACE_BLOCK), 0, s, a);
+  if (pr.face_blocks[2] > 0) hipLaunchKernelGGL((k_adj_face<2, RECON, SHIFT>), dim3((unsigned)pr.face_blocks[2]), dim3(FACE_BLOCK), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_faces_r(const AdjArgs& a, int recon, const Prepared& pr, hipStream_t s) {
+  const bool sh = a.beta != nullptr;
+  switch (recon) {
+    case GRMHD_RECON_MINMOD:
+      return sh ? launch_adj_faces<GRMHD_RECON_MINMOD, true>(a, pr, s) : launch_adj_faces<GRMHD_RECON_MINMOD, false>(a, pr, s);
+    case GRMHD_RECON_WENO5:
+      return sh ? launch_adj_faces<GRMHD_RECON_WENO5, true>(a, pr, s) : launch_adj_faces<GRMHD_RECON_WENO5, false>(a, pr, s);
+    default:
+      return sh ? launch_adj_faces<GRMHD_RECON_WENOZ, true>(a, pr, s) : launch_adj_faces<GRMHD_RECON_WENOZ, false>(a, pr, s);
+  }
+}
+
+hipError_t launch_adj_cell(const AdjCellArgs& a, const Prepared& pr, hipStream_t s) {
+  if (a.beta)
+    hipLaunchKernelGGL((k_adj_cell<true>), dim3((unsigned)pr.c2p_blocks), dim3(C2P_BLOCK), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_adj_cell<false>), dim3((unsigned)pr.c2p_blocks), dim3(C2P_BLOCK), 0, s, a);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 extern "C" {
@@ -623,8 +992,9 @@ int grmhd_domain_prepare(const grmhd_domain* dom, void* stream) {
   KBox* kb = reinterpret_cast<KBox*>(buf.data() + sizeof(TableHeader));
   int32_t* c2p = reinterpret_cast<int32_t*>(buf.data() + sizeof(TableHeader) + sizeof(KBox) * nb);
   int32_t* tp = c2p + (nb + 1);
+  int32_t* fp = tp + NTILE * (nb + 1);
   Prepared pr;
-  int64_t acc_c2p = 0, acc_t[NTILE] = {0, 0, 0};
+  int64_t acc_c2p = 0, acc_t[NTILE] = {0, 0, 0}, acc_f[3] = {0, 0, 0};
   for (int b = 0; b < nb; ++b) {
     const grmhd_box& x = dom->box[b];
     KBox& k = kb[b];
@@ -654,12 +1024,22 @@ int grmhd_domain_prepare(const grmhd_domain* dom, void* stream) {
       acc_t[t] += int64_t((x.n[0] + TILE_X[t] - 1) / TILE_X[t]) * ((x.n[1] + TILE_Y[t] - 1) / TILE_Y[t]) *
                   ((x.n[2] + TILE_Z[t] - 1) / TILE_Z[t]);
     }
+    for (int d = 0; d < 3; ++d) {
+      fp[d * (nb + 1) + b] = (int32_t)acc_f[d];
+      const int64_t nf = int64_t(x.n[0] + (d == 0)) * (x.n[1] + (d == 1)) * (x.n[2] + (d == 2));
+      acc_f[d] += (nf + FACE_BLOCK - 1) / FACE_BLOCK;
+    }
   }
   if (acc_c2p >= (int64_t(1) << 31)) return invalid("too many cells");
   c2p[nb] = (int32_t)acc_c2p;
   for (int t = 0; t < NTILE; ++t) {
     if (acc_t[t] >= (int64_t(1) << 31)) return invalid("too many tiles");
     tp[t * (nb + 1) + nb] = (int32_t)acc_t[t];
+  }
+  for (int d = 0; d < 3; ++d) {
+    if (acc_f[d] >= (int64_t(1) << 31)) return invalid("too many faces");
+    fp[d * (nb + 1) + nb] = (int32_t)acc_f[d];
+    h->face_blocks[d] = acc_f[d];
   }
   h->magic = TABLE_MAGIC;
   h->hash = domain_hash(dom);
@@ -675,6 +1055,7 @@ int grmhd_domain_prepare(const grmhd_domain* dom, void* stream) {
   pr.nbox = nb;
   pr.c2p_blocks = acc_c2p;
   for (int t = 0; t < NTILE; ++t) pr.tiles[t] = acc_t[t];
+  for (int d = 0; d < 3; ++d) pr.face_blocks[d] = acc_f[d];
   std::lock_guard<std::mutex> lk(g_mu);
   g_prepared[dom->table] = pr;
   return GRMHD_OK;
@@ -727,7 +1108,7 @@ size_t grmhd_workspace_bytes(const grmhd_domain* dom, const grmhd_params* par, i
   (void)scheme;
   if (!dom || dom->cell_stride < 1) return 0;
   const size_t field = sizeof(double) * 8 * (size_t)dom->cell_stride;
-  return for_adjoint ? 4 * field : field;
+  return for_adjoint ? 2 * field : field;
 }
 
 int grmhd_rk_step(const grmhd_domain* dom, const grmhd_params* par, const grmhd_metric* met, double* U, double* P,
@@ -768,6 +1149,115 @@ int grmhd_rk_step(const grmhd_domain* dom, const grmhd_params* par, const grmhd_
     double* ck = (stage_ckpt && st + 1 < nst) ? stage_ckpt + (st + 1) * fsz : nullptr;
     e = launch_c2p(dom, pr, ph, met, a.Uout, P, ck, nullptr, n_fail, s);
     if (e != hipSuccess) return fail_hip(e, "k_con2prim");
+  }
+  return GRMHD_OK;
+}
+
+
+int grmhd_con2prim_adjoint(const grmhd_domain* dom, const grmhd_params* par, const grmhd_metric* met, const double* P,
+                           const double* gP, double* gU, void* stream) {
+  Prepared pr;
+  KPhys ph;
+  int r;
+  if ((r = check_domain(dom, pr)) || (r = check_params(par, nullptr, ph)) || (r = check_metric(met, false))) return r;
+  if (!P || !gP || !gU) return invalid("null P, gP or gU");
+  AdjCellArgs a;
+  a.tab = make_table(dom);
+  a.P = P;
+  a.V = const_cast<double*>(gP);
+  a.Gn = gU;
+  a.Pbar = nullptr;
+  a.alpha = met->gamma;  // not read in this mode (only the spatial metric enters dU/dP)
+  a.beta = nullptr;
+  a.gamma = met->gamma;
+  a.cs = dom->cell_stride;
+  a.vs = dom->vert_stride;
+  a.ph = ph;
+  a.cstage = 1.0;
+  a.dt = 0.0;
+  a.first_stage = 0;
+  a.mode = 1;
+  hipError_t e = launch_adj_cell(a, pr, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? GRMHD_OK : fail_hip(e, "k_adj_cell");
+}
+
+int grmhd_rk_step_adjoint(const grmhd_domain* dom, const grmhd_params* par, const grmhd_metric* met,
+                          const double* stage_ckpt, double* P, double dt, int32_t scheme, const double* gU_out,
+                          double* gU_in, void* ws, size_t ws_bytes, void* stream) {
+  Prepared pr;
+  KPhys ph;
+  int r;
+  if ((r = check_domain(dom, pr)) || (r = check_params(par, dom, ph)) || (r = check_metric(met, true))) return r;
+  if (!stage_ckpt || !P || !gU_out || !gU_in) return invalid("null checkpoint, P or adjoint vector");
+  if (gU_out == gU_in) return invalid("gU_out and gU_in must not alias");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return invalid("dt must be positive and finite");
+  if (scheme != GRMHD_SSPRK3 && scheme != GRMHD_SSPRK2) return invalid("unknown time integrator");
+  if (!ws) return invalid("null workspace");
+  if (ws_bytes < grmhd_workspace_bytes(dom, par, scheme, 1)) {
+    g_last_error = "workspace too small";
+    return GRMHD_EWORKSPACE;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  static const double c3[3] = {1.0, 0.25, 2.0 / 3.0};
+  static const double c2[2] = {1.0, 0.5};
+  const double* cst = scheme == GRMHD_SSPRK2 ? c2 : c3;
+  const int nst = scheme == GRMHD_SSPRK2 ? 2 : 3;
+  const size_t fsz = 8 * (size_t)dom->cell_stride;
+  double* V = static_cast<double*>(ws);
+  double* Pbar = V + fsz;
+  const Table tab = make_table(dom);
+  const unsigned cb = (unsigned)pr.c2p_blocks;
+  hipLaunchKernelGGL(k_copy, dim3(cb), dim3(C2P_BLOCK), 0, s, tab, gU_out, V, dom->cell_stride);
+  hipLaunchKernelGGL(k_fill, dim3(cb), dim3(C2P_BLOCK), 0, s, tab, gU_in, dom->cell_stride, 0.0);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail_hip(e, "adjoint setup");
+  for (int st = nst - 1; st >= 0; --st) {
+    // primitives of the stage state (checkpoints are not modified)
+    CellArgs ca;
+    ca.tab = tab;
+    ca.U = const_cast<double*>(stage_ckpt + st * fsz);
+    ca.P = P;
+    ca.write_u = 0;
+    ca.ckpt = nullptr;
+    ca.status = nullptr;
+    ca.n_fail = nullptr;
+    ca.gamma = met->gamma;
+    ca.cs = dom->cell_stride;
+    ca.vs = dom->vert_stride;
+    ca.ph = ph;
+    hipLaunchKernelGGL(k_con2prim, dim3(cb), dim3(C2P_BLOCK), 0, s, ca);
+    hipLaunchKernelGGL(k_fill, dim3(cb), dim3(C2P_BLOCK), 0, s, tab, Pbar, dom->cell_stride, 0.0);
+    AdjArgs fa;
+    fa.tab = tab;
+    fa.P = P;
+    fa.V = V;
+    fa.Pbar = Pbar;
+    fa.alpha = met->alpha;
+    fa.beta = met->beta;
+    fa.gamma = met->gamma;
+    fa.cs = dom->cell_stride;
+    fa.vs = dom->vert_stride;
+    fa.ph = ph;
+    e = launch_adj_faces_r(fa, par->recon, pr, s);
+    if (e != hipSuccess) return fail_hip(e, "k_adj_face");
+    AdjCellArgs a;
+    a.tab = tab;
+    a.P = P;
+    a.V = V;
+    a.Gn = gU_in;
+    a.Pbar = Pbar;
+    a.alpha = met->alpha;
+    a.beta = met->beta;
+    a.gamma = met->gamma;
+    a.cs = dom->cell_stride;
+    a.vs = dom->vert_stride;
+    a.ph = ph;
+    a.cstage = cst[st];
+    a.dt = dt;
+    a.first_stage = (st == 0);
+    a.mode = 0;
+    e = launch_adj_cell(a, pr, s);
+    if (e != hipSuccess) return fail_hip(e, "k_adj_cell");
   }
   return GRMHD_OK;
 }

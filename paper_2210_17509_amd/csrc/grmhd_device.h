@@ -30,6 +30,8 @@ struct KBox {
 };
 static_assert(sizeof(KBox) % 8 == 0, "KBox alignment");
 
+constexpr int FACE_BLOCK = 256;
+
 struct TableHeader {
   uint64_t magic;
   uint64_t hash;
@@ -37,13 +39,16 @@ struct TableHeader {
   int32_t pad;
   int64_t c2p_blocks;
   int64_t tiles[NTILE];
+  int64_t face_blocks[3];
 };
 
 // Device table: header | KBox[nbox] | int32 c2p_prefix[nbox+1] | int32 tile_prefix[NTILE][nbox+1]
+//               | int32 face_prefix[3][nbox+1]
 struct Table {
   const KBox* box;
   const int32_t* c2p_prefix;
   const int32_t* tile_prefix;  // [NTILE][nbox+1]
+  const int32_t* face_prefix;  // [3][nbox+1], blocks of FACE_BLOCK faces per direction
   int32_t nbox;
 };
 
@@ -125,8 +130,8 @@ template <typename R> struct SideState {
   R v2, iW, W, B2, ab0, b2, p, rhoh;
 };
 
-template <typename R>
-__device__ __forceinline__ void side_v2(const FaceMetric<R>& m, const R* P, SideState<R>& s) {
+template <typename R, typename RM>
+__device__ __forceinline__ void side_v2(const FaceMetric<RM>& m, const R* P, SideState<R>& s) {
 #pragma unroll
   for (int i = 0; i < 3; ++i)
     s.vlow[i] = m.g[sidx(i, 0)] * P[1] + m.g[sidx(i, 1)] * P[2] + m.g[sidx(i, 2)] * P[3];
@@ -140,8 +145,8 @@ template <typename R> __device__ __forceinline__ bool side_ok(const R* P, R v2) 
   return fin && (P[0] > R(0)) && (P[4] > R(0)) && (v2 < R(1));
 }
 
-template <typename R>
-__device__ __forceinline__ void side_rest(const FaceMetric<R>& m, const R* P, R gm1, SideState<R>& s) {
+template <typename R, typename RM>
+__device__ __forceinline__ void side_rest(const FaceMetric<RM>& m, const R* P, RM gm1, SideState<R>& s) {
 #pragma unroll
   for (int i = 0; i < 3; ++i)
     s.Blow[i] = m.g[sidx(i, 0)] * P[5] + m.g[sidx(i, 1)] * P[6] + m.g[sidx(i, 2)] * P[7];
@@ -158,8 +163,8 @@ __device__ __forceinline__ void side_rest(const FaceMetric<R>& m, const R* P, R 
 // Bounds of the characteristic speeds in direction D: the 3+1 hydrodynamic
 // eigenvalues with the sound speed replaced by the fast magnetosonic bound
 // c_f^2 = c_s^2 + c_a^2 - c_s^2 c_a^2.
-template <int D, typename R>
-__device__ __forceinline__ void side_speeds(const FaceMetric<R>& m, const R* P, const SideState<R>& s, R gam, R& lp,
+template <int D, typename R, typename RM>
+__device__ __forceinline__ void side_speeds(const FaceMetric<RM>& m, const R* P, const SideState<R>& s, RM gam, R& lp,
                                             R& lm) {
   const R cs2 = gam * s.p / s.rhoh;
   const R ca2 = s.b2 / (s.rhoh + s.b2);
@@ -169,17 +174,17 @@ __device__ __forceinline__ void side_speeds(const FaceMetric<R>& m, const R* P, 
   const R disc = (R(1) - s.v2) * (m.gdd * den - vd * vd * (R(1) - cf2));
   const R root = sqrt_r(cf2 * rmax(disc, R(0)));
   const R base = vd * (R(1) - cf2);
-  const R ad = m.alpha / den;
+  const R ad = R(m.alpha) / den;
   lp = ad * (base + root) - m.beta[D];
   lm = ad * (base - root) - m.beta[D];
 }
 
 // Conserved variables and the direction-D flux, Eqs. (p2c1)-(p2c4) and
 // (definition-of-flux) with v~ = v - beta / alpha.
-template <int D, typename R>
-__device__ __forceinline__ void side_cons_flux(const FaceMetric<R>& m, const R* P, const SideState<R>& s, R U[8],
+template <int D, typename R, typename RM>
+__device__ __forceinline__ void side_cons_flux(const FaceMetric<RM>& m, const R* P, const SideState<R>& s, R U[8],
                                                R F[8]) {
-  const R sg = m.sqrtg;
+  const RM sg = m.sqrtg;
   const R W2 = s.W * s.W;
   const R rhohs = s.rhoh + s.b2;
   const R Ps = s.p + R(0.5) * s.b2;
@@ -192,8 +197,8 @@ __device__ __forceinline__ void side_cons_flux(const FaceMetric<R>& m, const R* 
   U[4] = sg * (rhohs * W2 - Ps - s.ab0 * s.ab0) - U[0];
 #pragma unroll
   for (int k = 0; k < 3; ++k) U[5 + k] = sg * P[5 + k];
-  const R a = m.alpha;
-  const R ia = R(1) / a;
+  const RM a = m.alpha;
+  const RM ia = RM(1) / a;
   R vt[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) vt[i] = P[1 + i] - m.beta[i] * ia;
@@ -333,101 +338,113 @@ __device__ __forceinline__ double edge_deriv(const double* __restrict__ f, int v
   return 0.25 * ((s0 + s1) + (s2 + s3)) * idx;
 }
 
+// First derivatives of the vertex metric at a cell centre.
+struct MetricDeriv {
+  double da[3], dg[3][6], db[3][3];
+};
+
+template <bool SHIFT>
+__device__ __forceinline__ void metric_deriv(const double* __restrict__ alpha, const double* __restrict__ beta,
+                                             const double* __restrict__ gamma, int64_t vs, int vb, int VX, int VXY,
+                                             const double* inv_dx, MetricDeriv& md) {
+  const int st[3] = {1, VX, VXY};
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    const int se = st[e], sa = st[(e + 1) % 3], sb = st[(e + 2) % 3];
+    md.da[e] = edge_deriv(alpha, vb, se, sa, sb, inv_dx[e]);
+#pragma unroll
+    for (int q = 0; q < 6; ++q) md.dg[e][q] = edge_deriv(gamma + q * vs, vb, se, sa, sb, inv_dx[e]);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) md.db[e][q] = SHIFT ? edge_deriv(beta + q * vs, vb, se, sa, sb, inv_dx[e]) : 0.0;
+  }
+}
+
 // Static-metric source terms of Eq. (definition-of-source) in 3+1 form:
 //   S_Sj  = alpha sqrt(g) [T^00 (beta^i beta^k d_j g_ik / 2 - alpha d_j alpha)
 //           + T^0i beta^k d_j g_ik + T^0_i d_j beta^i + T^ik d_j g_ik / 2]
 //   S_tau = alpha sqrt(g) [T^00 (beta^i beta^j K_ij - beta^i d_i alpha)
 //           + T^0i (2 beta^j K_ij - d_i alpha) + T^ij K_ij]
 // with K_ij = (gamma_jk d_i beta^k + gamma_ik d_j beta^k + beta^k d_k gamma_ij) / (2 alpha)
-// for a time-independent slice; S_D = S_B = 0.
-template <bool SHIFT>
-__device__ __forceinline__ void sources(const double* __restrict__ alpha, const double* __restrict__ beta,
-                                        const double* __restrict__ gamma, int64_t vs, int vb, int VX, int VXY,
-                                        const double* inv_dx, const CentreMetric& m, const double* P, double gam,
-                                        double S[8]) {
-  const int st[3] = {1, VX, VXY};
-  double da[3], dg[3][6], db[3][3];
-#pragma unroll
-  for (int e = 0; e < 3; ++e) {
-    const int se = st[e], sa = st[(e + 1) % 3], sb = st[(e + 2) % 3];
-    da[e] = edge_deriv(alpha, vb, se, sa, sb, inv_dx[e]);
-#pragma unroll
-    for (int q = 0; q < 6; ++q) dg[e][q] = edge_deriv(gamma + q * vs, vb, se, sa, sb, inv_dx[e]);
-#pragma unroll
-    for (int q = 0; q < 3; ++q) db[e][q] = SHIFT ? edge_deriv(beta + q * vs, vb, se, sa, sb, inv_dx[e]) : 0.0;
-  }
+// for a time-independent slice; S_D = S_B = 0.  T = double, or a dual number
+// for the adjoint.
+template <bool SHIFT, typename T>
+__device__ __forceinline__ void sources_T(const CentreMetric& m, const MetricDeriv& md, const T* P, double gam,
+                                          T S[8]) {
+  const double* da = md.da;
   // 4-velocity, magnetic 4-vector and T^{mu nu} (Eq. (mhd-stress-energy-tensor))
-  double vlow[3], Blow[3];
+  T vlow[3], Blow[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
     vlow[i] = m.g[sidx(i, 0)] * P[1] + m.g[sidx(i, 1)] * P[2] + m.g[sidx(i, 2)] * P[3];
     Blow[i] = m.g[sidx(i, 0)] * P[5] + m.g[sidx(i, 1)] * P[6] + m.g[sidx(i, 2)] * P[7];
   }
-  const double v2 = vlow[0] * P[1] + vlow[1] * P[2] + vlow[2] * P[3];
-  const double iW = sqrt(1.0 - v2);
-  const double W = 1.0 / iW;
-  const double B2 = Blow[0] * P[5] + Blow[1] * P[6] + Blow[2] * P[7];
-  const double Bv = Blow[0] * P[1] + Blow[1] * P[2] + Blow[2] * P[3];
+  const T v2 = vlow[0] * P[1] + vlow[1] * P[2] + vlow[2] * P[3];
+  const T iW = sqrt_r(T(1.0) - v2);
+  const T W = T(1.0) / iW;
+  const T B2 = Blow[0] * P[5] + Blow[1] * P[6] + Blow[2] * P[7];
+  const T Bv = Blow[0] * P[1] + Blow[1] * P[2] + Blow[2] * P[3];
   const double ia = 1.0 / m.alpha;
-  const double b0 = W * Bv * ia;
-  const double b2 = B2 * (iW * iW) + Bv * Bv;
-  const double p = (gam - 1.0) * P[0] * P[4];
-  const double rhohs = P[0] * (1.0 + P[4]) + p + b2;
-  const double Ps = p + 0.5 * b2;
-  const double u0 = W * ia;
-  double u[3], b[3];
+  const T b0 = W * Bv * ia;
+  const T b2 = B2 * (iW * iW) + Bv * Bv;
+  const T p = (gam - 1.0) * P[0] * P[4];
+  const T rhohs = P[0] * (T(1.0) + P[4]) + p + b2;
+  const T Ps = p + T(0.5) * b2;
+  const T u0 = W * ia;
+  T u[3], b[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
     u[i] = W * (P[1 + i] - m.beta[i] * ia);
     b[i] = (P[5 + i] + m.alpha * b0 * u[i]) * iW;
   }
   const double ia2 = ia * ia;
-  const double T00 = rhohs * u0 * u0 - Ps * ia2 - b0 * b0;
-  double T0[3], Tij[6];
+  const T T00 = rhohs * u0 * u0 - Ps * ia2 - b0 * b0;
+  T T0[3], Tij[6];
 #pragma unroll
-  for (int i = 0; i < 3; ++i) T0[i] = rhohs * u0 * u[i] + Ps * m.beta[i] * ia2 - b0 * b[i];
+  for (int i = 0; i < 3; ++i) T0[i] = rhohs * u0 * u[i] + Ps * (m.beta[i] * ia2) - b0 * b[i];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = i; j < 3; ++j)
       Tij[sidx(i, j)] = rhohs * u[i] * u[j] + Ps * (m.gi[sidx(i, j)] - m.beta[i] * m.beta[j] * ia2) - b[i] * b[j];
   const double as = m.alpha * m.sqrtg;
-  S[0] = 0.0;
-  S[5] = S[6] = S[7] = 0.0;
+  S[0] = T(0.0);
+  S[5] = S[6] = S[7] = T(0.0);
   if (!SHIFT) {
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-      double tdg = 0.0;
+      T tdg = T(0.0);
 #pragma unroll
       for (int i = 0; i < 3; ++i)
 #pragma unroll
-        for (int k = 0; k < 3; ++k) tdg += Tij[sidx(i, k)] * dg[j][sidx(i, k)];
-      S[1 + j] = as * (0.5 * tdg - m.alpha * T00 * da[j]);
+        for (int k = 0; k < 3; ++k) tdg = tdg + Tij[sidx(i, k)] * md.dg[j][sidx(i, k)];
+      S[1 + j] = as * (T(0.5) * tdg - m.alpha * T00 * da[j]);
     }
     S[4] = -as * (T0[0] * da[0] + T0[1] * da[1] + T0[2] * da[2]);
   } else {
     const double* be = m.beta;
-    double blw[3], T0low[3];
+    double blw[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i) blw[i] = m.g[sidx(i, 0)] * be[0] + m.g[sidx(i, 1)] * be[1] + m.g[sidx(i, 2)] * be[2];
+    T T0low[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i)
       T0low[i] = T00 * blw[i] + T0[0] * m.g[sidx(0, i)] + T0[1] * m.g[sidx(1, i)] + T0[2] * m.g[sidx(2, i)];
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-      double bbdg = 0.0, tdg = 0.0, t0bdg = 0.0, t0db = 0.0;
+      double bbdg = 0.0;
+      T tdg = T(0.0), t0bdg = T(0.0), t0db = T(0.0);
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
-        t0db += T0low[i] * db[j][i];
+        t0db = t0db + T0low[i] * md.db[j][i];
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-          const double dgik = dg[j][sidx(i, k)];
+          const double dgik = md.dg[j][sidx(i, k)];
           bbdg += be[i] * be[k] * dgik;
-          tdg += Tij[sidx(i, k)] * dgik;
-          t0bdg += T0[i] * be[k] * dgik;
+          tdg = tdg + Tij[sidx(i, k)] * dgik;
+          t0bdg = t0bdg + T0[i] * (be[k] * dgik);
         }
       }
-      S[1 + j] = as * (T00 * (0.5 * bbdg - m.alpha * da[j]) + t0bdg + t0db + 0.5 * tdg);
+      S[1 + j] = as * (T00 * (0.5 * bbdg - m.alpha * da[j]) + t0bdg + t0db + T(0.5) * tdg);
     }
     double K[6];
     const double i2a = 0.5 * ia;
@@ -437,10 +454,12 @@ __device__ __forceinline__ void sources(const double* __restrict__ alpha, const 
       for (int j = i; j < 3; ++j) {
         double t = 0.0;
 #pragma unroll
-        for (int k = 0; k < 3; ++k) t += m.g[sidx(j, k)] * db[i][k] + m.g[sidx(i, k)] * db[j][k] + be[k] * dg[k][sidx(i, j)];
+        for (int k = 0; k < 3; ++k)
+          t += m.g[sidx(j, k)] * md.db[i][k] + m.g[sidx(i, k)] * md.db[j][k] + be[k] * md.dg[k][sidx(i, j)];
         K[sidx(i, j)] = t * i2a;
       }
-    double bbK = 0.0, bda = 0.0, t0i = 0.0, tK = 0.0;
+    double bbK = 0.0, bda = 0.0;
+    T t0i = T(0.0), tK = T(0.0);
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       bda += be[i] * da[i];
@@ -449,34 +468,37 @@ __device__ __forceinline__ void sources(const double* __restrict__ alpha, const 
       for (int j = 0; j < 3; ++j) {
         bbK += be[i] * be[j] * K[sidx(i, j)];
         bK += be[j] * K[sidx(i, j)];
-        tK += Tij[sidx(i, j)] * K[sidx(i, j)];
+        tK = tK + Tij[sidx(i, j)] * K[sidx(i, j)];
       }
-      t0i += T0[i] * (2.0 * bK - da[i]);
+      t0i = t0i + T0[i] * (2.0 * bK - da[i]);
     }
     S[4] = as * (T00 * (bbK - bda) + t0i + tK);
   }
 }
 
-// ---------------------------------------------------------------- prim -> cons at a cell (FP64)
+// ---------------------------------------------------------------- prim -> cons at a cell
 
-__device__ __forceinline__ void p2c_cell(const double* g, double sqrtg, double gm1, const double* P, double U[8]) {
-  double vlow[3], Blow[3];
+// Eqs. (p2c1)-(p2c4) at a cell centre; T = double, or a dual number for the
+// Jacobian dU/dP used by the adjoint.
+template <typename T>
+__device__ __forceinline__ void p2c_cell(const double* g, double sqrtg, double gm1, const T* P, T U[8]) {
+  T vlow[3], Blow[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
     vlow[i] = g[sidx(i, 0)] * P[1] + g[sidx(i, 1)] * P[2] + g[sidx(i, 2)] * P[3];
     Blow[i] = g[sidx(i, 0)] * P[5] + g[sidx(i, 1)] * P[6] + g[sidx(i, 2)] * P[7];
   }
-  const double v2 = vlow[0] * P[1] + vlow[1] * P[2] + vlow[2] * P[3];
-  const double iW = sqrt(1.0 - v2);
-  const double W = 1.0 / iW;
-  const double B2 = Blow[0] * P[5] + Blow[1] * P[6] + Blow[2] * P[7];
-  const double Bv = Blow[0] * P[1] + Blow[1] * P[2] + Blow[2] * P[3];
-  const double ab0 = W * Bv;
-  const double b2 = (B2 + ab0 * ab0) * (iW * iW);
-  const double p = gm1 * P[0] * P[4];
-  const double rhohs = P[0] * (1.0 + P[4]) + p + b2;
-  const double Ps = p + 0.5 * b2;
-  const double W2 = W * W;
+  const T v2 = vlow[0] * P[1] + vlow[1] * P[2] + vlow[2] * P[3];
+  const T iW = sqrt_r(T(1.0) - v2);
+  const T W = T(1.0) / iW;
+  const T B2 = Blow[0] * P[5] + Blow[1] * P[6] + Blow[2] * P[7];
+  const T Bv = Blow[0] * P[1] + Blow[1] * P[2] + Blow[2] * P[3];
+  const T ab0 = W * Bv;
+  const T b2 = (B2 + ab0 * ab0) * (iW * iW);
+  const T p = gm1 * P[0] * P[4];
+  const T rhohs = P[0] * (T(1.0) + P[4]) + p + b2;
+  const T Ps = p + T(0.5) * b2;
+  const T W2 = W * W;
   U[0] = sqrtg * P[0] * W;
 #pragma unroll
   for (int j = 0; j < 3; ++j) U[1 + j] = sqrtg * (rhohs * W2 * vlow[j] - ab0 * (Blow[j] * iW + ab0 * vlow[j]));

@@ -65,12 +65,15 @@ _lib.grmhd_workspace_bytes.restype = ctypes.c_size_t
 _lib.grmhd_strerror.argtypes = [ctypes.c_int]
 _lib.grmhd_strerror.restype = ctypes.c_char_p
 _lib.grmhd_last_error.restype = ctypes.c_char_p
+_lib.grmhd_con2prim_adjoint.argtypes = [_pd, _pp, _pm, _P, _P, _P, _P]
+_lib.grmhd_rk_step_adjoint.argtypes = [_pd, _pp, _pm, _P, _P, ctypes.c_double, ctypes.c_int32, _P, _P, _P,
+                                       ctypes.c_size_t, _P]
 _lib.grmhd_timing_enable.argtypes = [ctypes.c_int32]
 _lib.grmhd_timing_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
 
 EXPORTED = ["grmhd_domain_table_bytes", "grmhd_domain_prepare", "grmhd_prim2con", "grmhd_con2prim", "grmhd_rhs",
             "grmhd_rk_step", "grmhd_workspace_bytes", "grmhd_strerror", "grmhd_last_error", "grmhd_timing_enable",
-            "grmhd_timing_read"]
+            "grmhd_timing_read", "grmhd_con2prim_adjoint", "grmhd_rk_step_adjoint"]
 
 
 class GrmhdError(RuntimeError):
@@ -219,3 +222,21 @@ def grmhd_timing_read():
     n = (ctypes.c_int64 * 2)()
     _check(_lib.grmhd_timing_read(ms, n))
     return {"stage": (ms[0], n[0]), "con2prim": (ms[1], n[1])}
+
+
+def grmhd_con2prim_adjoint(dom, params, met, P, gP, gU, stream=None):
+    _check(_lib.grmhd_con2prim_adjoint(ctypes.byref(dom.c), ctypes.byref(_par(params)), ctypes.byref(met.c), _ptr(P),
+                                       _ptr(gP), _ptr(gU), _stream(stream)))
+
+
+def grmhd_rk_step_adjoint(dom, params, met, stage_ckpt, P, dt, gU_out, gU_in, scheme=GRMHD_SSPRK3, ws=None,
+                          stream=None):
+    pc = _par(params)
+    need = grmhd_workspace_bytes(dom, pc, scheme, 1)
+    if ws is None:
+        ws = torch.empty((need + 7) // 8, dtype=torch.float64, device=gU_out.device)
+    _check(_lib.grmhd_rk_step_adjoint(ctypes.byref(dom.c), ctypes.byref(pc), ctypes.byref(met.c), _ptr(stage_ckpt),
+                                      _ptr(P), float(dt), int(scheme), _ptr(gU_out), _ptr(gU_in),
+                                      ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(ws.numel() * ws.element_size()),
+                                      _stream(stream)))
+    return ws

@@ -178,7 +178,7 @@ def test_ssprk2_and_checkpoints(orc):
 @pytest.mark.parametrize("recon", [I.RECON_MINMOD, I.RECON_WENO5, I.RECON_WENOZ])
 def test_uniform_state_bitwise(recon):
     state = [0.7, 0.3, -0.2, 0.1, 1.2, 0.5, -0.4, 0.8]
-    bc = (I.BC_OUTFLOW, I.BC_OUTFLOW, I.BC_PERIODIC, I.BC_PERIODIC, I.BC_OUTFLOW, I.BC_PERIODIC)
+    bc = (I.BC_OUTFLOW, I.BC_OUTFLOW, I.BC_PERIODIC, I.BC_PERIODIC, I.BC_OUTFLOW, I.BC_OUTFLOW)
     prob = T.build((21, 9, 6), T.uniform_fields(state), bc=bc, params=I.Params(recon=recon))
     d = H.Dev(prob)
     U0 = d.host(d.U).copy()

@@ -22,7 +22,7 @@ from tests import problems as T
 @pytest.mark.parametrize("shift", [False, True])
 def test_uniform_state_preserved_bitwise(orc, recon, shift):
     state = [0.7, 0.3, -0.2, 0.1, 1.2, 0.5, -0.4, 0.8]
-    bc = (I.BC_OUTFLOW, I.BC_OUTFLOW, I.BC_PERIODIC, I.BC_PERIODIC, I.BC_OUTFLOW, I.BC_PERIODIC)
+    bc = (I.BC_OUTFLOW, I.BC_OUTFLOW, I.BC_PERIODIC, I.BC_PERIODIC, I.BC_OUTFLOW, I.BC_OUTFLOW)
     met = T.conformal_metric(lambda X, Y, Z: np.ones_like(X),
                              beta_fn=(lambda X, Y, Z: [0.1 + 0 * X, -0.05 + 0 * X, 0.02 + 0 * X]) if shift else None)
     prob = T.build((6, 5, 4), T.uniform_fields(state), met, bc=bc, params=I.Params(recon=recon))
