@@ -24,11 +24,18 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6  # 256 CU x 2.4 GHz x 64 FP64 lanes x 2 (FMA = 2 
 # counted by running the method's routines on an op-counting scalar.
 FLOPS_PER_CELL = {0: 2364, 1: 5292, 2: 5484}   # minmod, WENO5, WENO5-Z
 
+# The headline metric: the plain-FP64 zone rate of the workload (value) and, in the
+# same line, the adjoint/forward time ratio of the 128^3 WENO5-Z adjoint workload.
+METRIC = "GRMHD zone-updates/s per RK stage vs FP64 plain; adjoint/forward time ratio"
+
 WORKLOADS = {
     # name: (builder kwargs, description)
     "curved256": dict(kind="config1", n=256, desc="static curved metric 256^3, WENO5, HLLE, FP64, SSPRK3"),
     "flat64": dict(kind="config0", n=64, desc="flat 64^3 with jump, minmod, HLLE, FP64, SSPRK3"),
     "curved384-mixed": dict(kind="config3", n=384, desc="static curved metric 384^3, WENO5, FP32 recon+HLLE"),
+    "curved384-fp64": dict(kind="config3-fp64", n=384,
+                           desc="static curved metric 384^3 (mixed-precision recipe and seed), WENO5, HLLE, FP64"),
+    "batched400": dict(kind="config2", n=0, desc="400 uneven boxes (edges 16..64, flat/curved), WENO5, FP64"),
 }
 
 
@@ -41,6 +48,10 @@ def make_problem(w):
         return I.config0(n=spec["n"])
     if spec["kind"] == "config3":
         return I.config3(n=spec["n"], steps=1)
+    if spec["kind"] == "config3-fp64":
+        return I.config3(n=spec["n"], steps=1, precision=I.PREC_FP64)
+    if spec["kind"] == "config2":
+        return I.config2()
     raise ValueError(w)
 
 
@@ -63,7 +74,7 @@ def cpu_baseline(w, budget_s=12.0):
     kind = WORKLOADS[w]["kind"]
     # probe the rate on a small cube, then size the sample
     def run(n):
-        p = I.config1(n=n) if kind in ("config1", "config3") else I.config0(n=n)
+        p = I.config1(n=n) if kind in ("config1", "config3", "config3-fp64", "config2") else I.config0(n=n)
         U, P = oracle.prim2con(p), p.P.copy()
         t = time.perf_counter()
         oracle.rk_step(p, U, P)
@@ -77,40 +88,215 @@ def cpu_baseline(w, budget_s=12.0):
             "sample": f"one SSPRK3 step of the same recipe on {n}^3 cells ({t:.1f} s wall, {threads} threads)"}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="curved256", choices=sorted(WORKLOADS))
-    ap.add_argument("--tile", type=int, default=-1)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py runs on exactly one GPU: this build has no multi-GPU path (asked for {args.gpus})",
-              file=sys.stderr)
-        sys.exit(2)
+KERNEL_SOURCES = ("paper_2210_17509_amd/csrc/grmhd_capi.hip", "paper_2210_17509_amd/csrc/grmhd_device.h",
+                  "include/grmhd.h")
 
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def hbm_summary_path(workload):
+    return os.path.join(ROOT, "profiles", f"k_stage_{workload}_hbm.txt")
+
+
+def committed_traffic(workload):
+    """HBM bytes per stage-kernel launch from the committed counter summary of this
+    workload, or None if there is none or the kernel sources changed since it was taken."""
+    path = hbm_summary_path(workload)
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip().split()[0] if v.strip() else ""
+    if kv.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    return float(kv["traffic_bytes_per_launch"])
+
+
+def _counter_rows(d, counter, name_part):
+    import csv
+    import glob
+    vals = []
+    for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        with open(f) as fh:
+            for r in csv.DictReader(fh):
+                if r["Counter_Name"] == counter and name_part in r["Kernel_Name"]:
+                    vals.append((r["Kernel_Name"], float(r["Counter_Value"])))
+    if not vals:
+        raise SystemExit(f"no {counter} rows for '{name_part}' under {d}")
+    return vals
+
+
+def hbm_summary(args):
+    """Write the HBM-traffic summary of the stage kernel from four rocprofv3 --pmc runs
+    (FETCH_SIZE and WRITE_SIZE of the workload, the same two of the 1 GiB copy)."""
+    fdir, wdir, cfdir, cwdir = args.hbm_summary
+    fetch = _counter_rows(fdir, "FETCH_SIZE", "k_stage")
+    write = _counter_rows(wdir, "WRITE_SIZE", "k_stage")
+    cf = [v for _, v in _counter_rows(cfdir, "FETCH_SIZE", "copyBuffer")]
+    cw = [v for _, v in _counter_rows(cwdir, "WRITE_SIZE", "copyBuffer")]
+    copy_kib = (1 << 30) / 1024.0
+    ff, fw = copy_kib / (sum(cf) / len(cf)), copy_kib / (sum(cw) / len(cw))
+    fk = sum(v for _, v in fetch) / len(fetch)
+    wk = sum(v for _, v in write) / len(write)
+    from paper_2210_17509_amd import inputs as I
+    spec = WORKLOADS[args.workload]
+    ncell = (spec["n"] ** 3) if spec["n"] else None
+    traffic = (fk * ff + wk * fw) * 1024.0
+    alg = stage_bytes_per_cell() * ncell if ncell else None
+    lines = [
+        f"# HBM traffic of the stage kernel, workload: {spec['desc']}",
+        "# FETCH_SIZE / WRITE_SIZE are KiB per dispatch; each is scaled by what the same counter",
+        "# reads for a plain 1 GiB device copy (bench.py --calibrate-copy).",
+        "# Commands (repository root, one MI355X):",
+        f"#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d F -o bench -- python bench.py --workload {args.workload} --steps 1 --warmup 0 --no-cpu-baseline --no-adjoint",
+        f"#   rocprofv3 --pmc WRITE_SIZE --output-format csv -d W -o bench -- python bench.py --workload {args.workload} --steps 1 --warmup 0 --no-cpu-baseline --no-adjoint",
+        "#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d CF -o copy -- python bench.py --calibrate-copy",
+        "#   rocprofv3 --pmc WRITE_SIZE --output-format csv -d CW -o copy -- python bench.py --calibrate-copy",
+        f"#   python bench.py --workload {args.workload} --hbm-summary F W CF CW",
+        f"kernel_source_sha256: {kernel_source_hash()}",
+        f"kernel: {fetch[0][0]}",
+        f"dispatches: {len(fetch)} (FETCH) {len(write)} (WRITE)",
+        f"fetch_kib_per_dispatch: {fk:.1f}",
+        f"write_kib_per_dispatch: {wk:.1f}",
+        f"copy_fetch_factor: {ff:.4f}",
+        f"copy_write_factor: {fw:.4f}",
+        f"traffic_bytes_per_launch: {traffic:.6e}",
+    ]
+    if alg:
+        lines += [f"algorithmic_bytes_per_launch: {alg:.6e} ({stage_bytes_per_cell():.1f} B x {ncell} cells)",
+                  f"traffic_over_algorithmic: {traffic / alg:.3f}"]
+    os.makedirs(os.path.dirname(hbm_summary_path(args.workload)), exist_ok=True)
+    with open(hbm_summary_path(args.workload), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def stats_summary(args):
+    """Write profiles/kernels_<workload>_stats.txt from a rocprofv3 --kernel-trace --stats folder."""
+    import csv
+    import glob
+    d, cmd = args.stats_summary
+    files = glob.glob(os.path.join(d, "**", "*kernel_stats.csv"), recursive=True)
+    if not files:
+        raise SystemExit(f"no kernel_stats.csv under {d}")
+    with open(files[0]) as fh:
+        rows = list(csv.DictReader(fh))
+    lines = [f"# rocprofv3 kernel statistics, workload: {WORKLOADS[args.workload]['desc']}",
+             "# Command (repository root, one MI355X):",
+             f"#   {cmd}",
+             f"kernel_source_sha256: {kernel_source_hash()}",
+             f"{'calls':>6} {'avg_ms':>10} {'min_ms':>10} {'max_ms':>10} {'share%':>7}  kernel"]
+    for r in rows[:12]:
+        lines.append(f"{int(r['Calls']):6d} {float(r['AverageNs']) / 1e6:10.4f} {float(r['MinNs']) / 1e6:10.4f} "
+                     f"{float(r['MaxNs']) / 1e6:10.4f} {float(r['Percentage']):7.2f}  {r['Name'][:150]}")
+    path = os.path.join(ROOT, "profiles", f"kernels_{args.workload}_stats.txt")
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    with open(path, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def calibrate_copy(nbytes=1 << 30, reps=3):
+    """A plain device-to-device copy of known size: what FETCH_SIZE / WRITE_SIZE read for
+    exactly nbytes read and nbytes written per launch."""
+    import torch
+    a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "launches": reps,
+                      "GBs_read_plus_write": 2 * nbytes / dt / 1e9}), flush=True)
+
+
+def adjoint_bench(args):
+    """Forward (10 SSPRK3 steps writing stage checkpoints) and reverse pass (10 adjoint
+    steps) of the 128^3 WENO5-Z workload; reports the time ratio."""
     import torch
     from paper_2210_17509_amd import grmhd as G
-
-    torch.cuda.set_device(0)
-    prob = make_problem(args.workload)
+    from paper_2210_17509_amd import inputs as I
+    prob = I.config4()
     dom = G.Domain.from_problem(prob)
     met = G.Metric.from_problem(prob)
     par = G.make_params(prob.params, tile=args.tile)
+    P0 = torch.as_tensor(prob.P, device="cuda").contiguous()
+    U0 = torch.zeros_like(P0)
+    G.grmhd_prim2con(dom, par, met, P0, U0)
+    steps = prob.steps
+    ck = torch.empty((steps, 3) + tuple(U0.shape), dtype=torch.float64, device="cuda")
+    ws = torch.empty(G.grmhd_workspace_bytes(dom, par) // 8, dtype=torch.float64, device="cuda")
+    wsa = torch.empty(G.grmhd_workspace_bytes(dom, par, 0, 1) // 8, dtype=torch.float64, device="cuda")
+    g_out = torch.randn(U0.shape, dtype=torch.float64, device="cuda")
+    g_in = torch.zeros_like(g_out)
+
+    def fwd():
+        U, P = U0.clone(), P0.clone()
+        for k in range(steps):
+            G.grmhd_rk_step(dom, par, met, U, P, prob.dt, 0, ck[k], ws=ws)
+        return P
+
+    def bwd(P):
+        a, b = g_out.clone(), g_in
+        for k in reversed(range(steps)):
+            G.grmhd_rk_step_adjoint(dom, par, met, ck[k], P, prob.dt, a, b, 0, ws=wsa)
+            a, b = b, a
+
+    P = fwd()
+    bwd(P)
+    torch.cuda.synchronize()
+    reps = max(1, args.steps // 10)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        P = fwd()
+    torch.cuda.synchronize()
+    tf = (time.perf_counter() - t0) / reps
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        bwd(P)
+    torch.cuda.synchronize()
+    tb = (time.perf_counter() - t0) / reps
+    ncell = prob.ninterior
+    return {"metric": "adjoint/forward time ratio", "value": tb / tf, "unit": "ratio",
+            "higher_is_better": False, "forward_ms": tf * 1e3, "backward_ms": tb * 1e3,
+            "forward_zone_updates_per_s": ncell * 3 * steps / tf,
+            "config": {"workload": "flat 128^3 smooth, WENO5-Z, 10 SSPRK3 steps with stage checkpoints, FP64",
+                       "cells": ncell}}
+
+
+def run_workload(name, args):
+    """Warm up, then time `steps` SSPRK3 steps of workload `name` (HIP events on every
+    stage and con2prim launch, wall clock around the whole timed region)."""
+    import torch
+    from paper_2210_17509_amd import grmhd as G
+    prob = make_problem(name)
+    dom = G.Domain.from_problem(prob)
+    met = G.Metric.from_problem(prob)
+    par = G.make_params(prob.params, tile=args.tile, schedule=args.schedule)
     P = torch.as_tensor(prob.P, device="cuda").contiguous()
     U = torch.zeros_like(P)
     nfail = torch.zeros(1, dtype=torch.int64, device="cuda")
     rate = torch.zeros(1, dtype=torch.float64, device="cuda")
-    ws = torch.empty(G.grmhd_workspace_bytes(dom, par) // 8, dtype=torch.float64, device="cuda")
     G.grmhd_prim2con(dom, par, met, P, U)
-    ncell = prob.ninterior
-
+    if args.autotune:
+        from paper_2210_17509_amd.autotune import autotune
+        par, _ = autotune(dom, par, met, U, P, prob.dt, reps=2)
+    ws = torch.empty(G.grmhd_workspace_bytes(dom, par) // 8, dtype=torch.float64, device="cuda")
     for _ in range(args.warmup):
         G.grmhd_rk_step(dom, par, met, U, P, prob.dt, max_rate=rate, n_fail=nfail, ws=ws)
     torch.cuda.synchronize()
-
     G.grmhd_timing_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -120,6 +306,65 @@ def main():
     wall = time.perf_counter() - t0
     times = G.grmhd_timing_read()
     G.grmhd_timing_enable(False)
+    return {"prob": prob, "ncell": prob.ninterior, "wall": wall, "times": times, "nfail": int(nfail.item()),
+            "par": par, "U": U, "P": P}
+
+
+def field_errors(prob, a, b):
+    """Per-field relative L-inf and L2 of a against b over interior cells (both (8, cells))."""
+    import numpy as np
+    from paper_2210_17509_amd import inputs as I
+    import torch
+    mask = torch.as_tensor(np.concatenate([I.interior_mask(bx).ravel() for bx in prob.boxes]), device=a.device)
+    d = (a - b)[:, mask]
+    r = b[:, mask]
+    linf = (d.abs().amax(dim=1) / r.abs().amax(dim=1).clamp_min(1e-300)).tolist()
+    l2 = (d.norm(dim=1) / r.norm(dim=1).clamp_min(1e-300)).tolist()
+    return {"rel_linf": linf, "rel_l2": l2}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="curved256", choices=sorted(WORKLOADS))
+    ap.add_argument("--tile", type=int, default=-1)
+    ap.add_argument("--schedule", type=int, default=0)
+    ap.add_argument("--autotune", action="store_true", help="pick tile shape and schedule by timing")
+    ap.add_argument("--compare", default=None, help="also time this workload and report the rate ratio")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--adjoint", action="store_true",
+                    help="adjoint workload: 128^3 WENO5-Z, 10 steps with checkpoints, then the reverse pass")
+    ap.add_argument("--no-adjoint", action="store_true", help="leave the adjoint/forward ratio out of the line")
+    ap.add_argument("--hbm-summary", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
+                    help="write profiles/k_stage_<workload>_hbm.txt from rocprofv3 --pmc output folders")
+    ap.add_argument("--stats-summary", nargs=2, metavar=("STATS_DIR", "COMMAND"),
+                    help="write profiles/kernels_<workload>_stats.txt from a rocprofv3 --stats folder")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="plain 1 GiB device copy (reference for HBM byte counters)")
+    args = ap.parse_args()
+    if args.hbm_summary:
+        return hbm_summary(args)
+    if args.stats_summary:
+        return stats_summary(args)
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU: this build has no multi-GPU path (asked for {args.gpus})",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2210_17509_amd import grmhd as G
+
+    torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        return calibrate_copy()
+    if args.adjoint:
+        print(json.dumps(adjoint_bench(args)), flush=True)
+        return
+    res = run_workload(args.workload, args)
+    prob, ncell, wall, times, nfail, par = res["prob"], res["ncell"], res["wall"], res["times"], res["nfail"], \
+        res["par"]
 
     stages = 3
     value = ncell * stages * args.steps / wall
@@ -130,7 +375,7 @@ def main():
     achieved = flops_per_launch / avg_stage_s / 1e12
     hbm_gbs = stage_bytes_per_cell() * ncell / avg_stage_s / 1e9
     out = {
-        "metric": "GRMHD zone-updates/s per RK stage",
+        "metric": METRIC,
         "value": value,
         "unit": "zone-updates/s per RK stage",
         "n_gpus": 1,
@@ -142,15 +387,30 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if prob.params.precision == 0 else "f64+f32",
         "data": "synthetic",
-        "config": {"workload": WORKLOADS[args.workload]["desc"], "cells": ncell, "stages_per_step": stages,
-                   "n_fail": int(nfail.item())},
+        "config": {"workload": WORKLOADS[args.workload]["desc"], "cells": ncell, "boxes": len(prob.boxes),
+                   "stages_per_step": stages, "n_fail": nfail, "tile": par.tile, "schedule": par.schedule},
         "kernels": {"stage_ms_avg": st_ms / max(st_n, 1), "stage_launches": st_n,
                     "con2prim_ms_avg": c2p_ms / max(c2p_n, 1), "con2prim_launches": c2p_n},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
+                     "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": committed_traffic(args.workload),
                      "kernel": "k_stage", "flops_per_cell": FLOPS_PER_CELL[prob.params.recon],
                      "algorithmic_hbm_GBs": hbm_gbs, "algorithmic_hbm_frac": hbm_gbs / HBM_PEAK_GBS},
     }
+    if args.compare:
+        ref = run_workload(args.compare, args)
+        out["compare"] = {"workload": WORKLOADS[args.compare]["desc"],
+                          "value": ref["ncell"] * stages * args.steps / ref["wall"],
+                          "ratio": value / (ref["ncell"] * stages * args.steps / ref["wall"])}
+        if ref["U"].shape == res["U"].shape and ref["prob"].P.shape == prob.P.shape:
+            # same grid and the same number of steps from the same initial data
+            out["compare"]["U_error_vs_compare"] = field_errors(prob, res["U"], ref["U"])
+            out["compare"]["P_error_vs_compare"] = field_errors(prob, res["P"], ref["P"])
+        del ref
+    del res
+    if not args.no_adjoint:
+        a = adjoint_bench(args)
+        out["adjoint_forward_ratio"] = a["value"]
+        out["adjoint"] = {k: a[k] for k in ("forward_ms", "backward_ms", "config")}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.workload)
     print(json.dumps(out), flush=True)

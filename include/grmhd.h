@@ -65,6 +65,9 @@ enum { GRMHD_FP64 = 0, GRMHD_MIXED = 1 };
 enum { GRMHD_SSPRK3 = 0, GRMHD_SSPRK2 = 1 };
 /* Stage-kernel tiles (cells per workgroup, x * y * z = 256): 0 = 16x4x4, 1 = 8x8x4, 2 = 64x2x2. */
 #define GRMHD_NTILE 3
+/* Stage-kernel scheduling in grmhd_rk_step: one workgroup per tile, or persistent
+ * workgroups popping tiles from per-XCD atomic queues kept in the workspace. */
+enum { GRMHD_SCHED_GRID = 0, GRMHD_SCHED_QUEUE = 1 };
 /* per-cell con2prim status */
 enum {
   GRMHD_C2P_OK = 0,        /* 3D Newton-Raphson converged */
@@ -105,7 +108,7 @@ typedef struct {
   int32_t wenoz_p;    /* WENO-Z exponent: 1 or 2 */
   int32_t c2p_maxit;  /* iteration cap of each con2prim method, e.g. 100 */
   int32_t tile;       /* stage-kernel tile shape: -1 = library choice, else 0 .. GRMHD_NTILE-1 */
-  int32_t pad;
+  int32_t schedule;   /* GRMHD_SCHED_GRID | GRMHD_SCHED_QUEUE (grmhd_rk_step only) */
   double eos_gamma;   /* Gamma-law EOS p = (Gamma - 1) rho eps, Gamma > 1 */
   double weno_eps;    /* WENO5-JS epsilon, e.g. 1e-6 */
   double wenoz_eps;   /* WENO5-Z epsilon, e.g. 1e-40 */

@@ -8,7 +8,8 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SRC = [os.path.join(HERE, "csrc", "grmhd_capi.hip")]
-DEPS = SRC + [os.path.join(HERE, "csrc", "grmhd_device.h"), os.path.join(ROOT, "include", "grmhd.h")]
+DEPS = SRC + [os.path.join(HERE, "csrc", h) for h in ("grmhd_device.h", "grmhd_adjoint.h")] + \
+    [os.path.join(ROOT, "include", "grmhd.h")]
 LIB = os.path.join(HERE, "libgrmhd.so")
 
 HIPCC_FLAGS = [

@@ -4,10 +4,11 @@
 //   J^T v = (dU/dP)^{-T} [ sum_faces (dF*/dP_stencil)^T Fbar + (dS/dP)^T v ],
 //   Fbar(face between cells c-1, c) = (v_c - v_{c-1}) / dx_d,
 // where con2prim is differentiated through the implicit-function theorem
-// (it inverts prim->cons, so dP/dU = (dU/dP)^{-1}).  Face Jacobians combine a
-// hand-derived gradient of each reconstruction with forward-mode dual numbers
-// (8 tangents per side) through the same side routines the forward kernel
-// runs.  Max/min branches follow the forward choice.
+// (it inverts prim->cons, so dP/dU = (dU/dP)^{-1}).  The face part is reverse
+// mode written by hand: the HLLE combine, then each side's flux, state and
+// speeds (side_vjp), then the gradient of the reconstruction, scattered onto
+// the stencil cells.  The cell part (sources) uses forward-mode dual numbers
+// DN<8>, one tangent per primitive.  Max/min branches follow the forward choice.
 #pragma once
 
 #include "grmhd_device.h"

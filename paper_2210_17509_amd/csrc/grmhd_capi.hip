@@ -30,6 +30,7 @@ using namespace gk;
 namespace {
 
 constexpr uint64_t TABLE_MAGIC = 0x47524d4844544231ull;  // "GRMHDTB1"
+constexpr size_t QUEUE_BYTES = 256;  // per-XCD tile-queue counters at the end of the step workspace
 
 // tile shapes of the stage kernel (TX * TY * TZ = 256)
 constexpr int TILE_X[NTILE] = {16, 8, 64};
@@ -51,6 +52,8 @@ struct StageArgs {
   int32_t mode;  // 0: Uout = dU/dt; 1: Uout = Un + c ((Us - Un) + dt dU/dt)
   KPhys ph;
   double* max_rate;
+  unsigned int* queue;  // non-null: persistent launch over per-XCD tile queues
+  int32_t persist_blocks;
 };
 
 struct CellArgs {
@@ -81,6 +84,14 @@ __device__ __forceinline__ void block_max_atomic(double v, double* target) {
 
 // ---------------------------------------------------------------- stage kernel
 
+// Global tile index for workgroup blk of a grid of n: workgroup blk runs on XCD
+// blk mod 8, which receives the contiguous tile range of its share.
+__device__ __forceinline__ int xcd_tile(int blk, int n) {
+  const int x = blk & 7, m = blk >> 3;
+  const int q = n >> 3, r = n & 7;
+  return x * q + (x < r ? x : r) + m;
+}
+
 template <int D, int RECON, typename R, bool SHIFT>
 __device__ __forceinline__ void face_flux(const StageArgs& a, const KBox& bx, const double* __restrict__ Pb,
                                           const double* __restrict__ alb, const double* __restrict__ beb,
@@ -96,12 +107,12 @@ __device__ __forceinline__ void face_flux(const StageArgs& a, const KBox& bx, co
                               : ng * bx.NXY + (j + ng) * bx.NX + (i + ng);
   constexpr int O0 = (RECON == GRMHD_RECON_MINMOD) ? 1 : 0;  // minmod reads cells c-2 .. c+1
   constexpr int O1 = (RECON == GRMHD_RECON_MINMOD) ? 5 : 6;
-  int idx[6];
+  uint32_t idx[6];
 #pragma unroll
   for (int o = O0; o < O1; ++o) {
     const int m = c + o - 3;
     const int mm = (m < 0) ? bx.mlo[D][m + 3] : (m >= nD ? bx.mhi[D][m - nD] : m);
-    idx[o] = base + mm * sD;
+    idx[o] = (uint32_t)(base + mm * sD);
   }
   R PL[8], PR[8];
 #pragma unroll
@@ -109,7 +120,7 @@ __device__ __forceinline__ void face_flux(const StageArgs& a, const KBox& bx, co
     const double* __restrict__ f = Pb + q * a.cs;
     R s[6];
 #pragma unroll
-    for (int o = O0; o < O1; ++o) s[o] = (R)f[idx[o]];
+    for (int o = O0; o < O1; ++o) s[o] = (R)ldg(f, idx[o]);
     if (RECON == GRMHD_RECON_MINMOD) {
       PL[q] = s[2] + R(0.5) * minmod(s[2] - s[1], s[3] - s[2]);
       PR[q] = s[3] - R(0.5) * minmod(s[3] - s[2], s[4] - s[3]);
@@ -138,12 +149,12 @@ __device__ __forceinline__ void face_flux(const StageArgs& a, const KBox& bx, co
   side_v2(m, PR, sR);
   if (!side_ok(PL, sL.v2)) {
 #pragma unroll
-    for (int q = 0; q < 8; ++q) PL[q] = (R)Pb[q * a.cs + idx[2]];
+    for (int q = 0; q < 8; ++q) PL[q] = (R)ldg(Pb + q * a.cs, idx[2]);
     side_v2(m, PL, sL);
   }
   if (!side_ok(PR, sR.v2)) {
 #pragma unroll
-    for (int q = 0; q < 8; ++q) PR[q] = (R)Pb[q * a.cs + idx[3]];
+    for (int q = 0; q < 8; ++q) PR[q] = (R)ldg(Pb + q * a.cs, idx[3]);
     side_v2(m, PR, sR);
   }
   const R gm1 = (R)a.ph.gm1, gam = (R)a.ph.gam;
@@ -217,13 +228,13 @@ __device__ __forceinline__ void direction_phase(const StageArgs& a, const KBox& 
 }
 
 template <int RECON, typename R, bool SHIFT, int TI>
-__global__ __launch_bounds__(256) void k_stage(StageArgs a) {
+__device__ __forceinline__ void stage_tile(const StageArgs& a, int tg,
+                                           double (*sF)[TileGeo<TILE_X[TI], TILE_Y[TI], TILE_Z[TI]>::maxslots()],
+                                           double& rate) {
   constexpr int TX = TILE_X[TI], TY = TILE_Y[TI], TZ = TILE_Z[TI];
-  using G = TileGeo<TX, TY, TZ>;
-  __shared__ double sF[8][G::maxslots()];
-  const int b = find_box(a.tab.tile_prefix + TI * (a.tab.nbox + 1), a.tab.nbox, blockIdx.x);
+  const int b = find_box(a.tab.tile_prefix + TI * (a.tab.nbox + 1), a.tab.nbox, tg);
   const KBox& bx = a.tab.box[b];
-  const int t = blockIdx.x - a.tab.tile_prefix[TI * (a.tab.nbox + 1) + b];
+  const int t = tg - a.tab.tile_prefix[TI * (a.tab.nbox + 1) + b];
   const int ntx = (bx.n[0] + TX - 1) / TX, nty = (bx.n[1] + TY - 1) / TY;
   const int org[3] = {(t % ntx) * TX, ((t / ntx) % nty) * TY, (t / (ntx * nty)) * TZ};
   const int tid = threadIdx.x;
@@ -237,7 +248,6 @@ __global__ __launch_bounds__(256) void k_stage(StageArgs a) {
   double acc[8];
 #pragma unroll
   for (int q = 0; q < 8; ++q) acc[q] = 0.0;
-  double rate = 0.0;
   direction_phase<0, RECON, R, SHIFT, TX, TY, TZ>(a, bx, Pb, alb, beb, gab, org, l, valid, sF, acc, rate);
   direction_phase<1, RECON, R, SHIFT, TX, TY, TZ>(a, bx, Pb, alb, beb, gab, org, l, valid, sF, acc, rate);
   direction_phase<2, RECON, R, SHIFT, TX, TY, TZ>(a, bx, Pb, alb, beb, gab, org, l, valid, sF, acc, rate);
@@ -251,22 +261,60 @@ __global__ __launch_bounds__(256) void k_stage(StageArgs a) {
     metric_deriv<SHIFT>(alb, beb, gab, a.vs, vb, bx.VX, bx.VXY, bx.inv_dx, md);
     double P[8], S[8];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) P[q] = Pb[q * a.cs + c];
+    for (int q = 0; q < 8; ++q) P[q] = ldg(Pb + q * a.cs, (uint32_t)c);
     sources_T<SHIFT>(cm, md, P, a.ph.gam, S);
-    const int64_t cc = bx.cell_off + c;
     if (a.mode == 0) {
 #pragma unroll
-      for (int q = 0; q < 8; ++q) a.Uout[q * a.cs + cc] = acc[q] + S[q];
+      for (int q = 0; q < 8; ++q) stg(a.Uout + q * a.cs + bx.cell_off, (uint32_t)c, acc[q] + S[q]);
     } else {
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
-        const double un = a.Un[q * a.cs + cc];
-        const double us = a.Us[q * a.cs + cc];
-        a.Uout[q * a.cs + cc] = un + a.cstage * ((us - un) + a.dt * (acc[q] + S[q]));
+        const double un = ldg(a.Un + q * a.cs + bx.cell_off, (uint32_t)c);
+        const double us = ldg(a.Us + q * a.cs + bx.cell_off, (uint32_t)c);
+        stg(a.Uout + q * a.cs + bx.cell_off, (uint32_t)c, un + a.cstage * ((us - un) + a.dt * (acc[q] + S[q])));
       }
     }
   }
+}
+
+// One workgroup per tile.  Workgroups are dispatched round-robin over the 8
+// XCDs; each XCD gets a contiguous run of tiles so tiles sharing halos share an L2.
+template <int RECON, typename R, bool SHIFT, int TI>
+__global__ __launch_bounds__(256) void k_stage(StageArgs a) {
+  using G = TileGeo<TILE_X[TI], TILE_Y[TI], TILE_Z[TI]>;
+  __shared__ double sF[8][G::maxslots()];
+  double rate = 0.0;
+  stage_tile<RECON, R, SHIFT, TI>(a, xcd_tile(blockIdx.x, gridDim.x), sF, rate);
   if (a.max_rate) block_max_atomic(rate, a.max_rate);
+}
+
+// Persistent workgroups: each pops tiles from the queue of its XCD (a
+// contiguous tile range per XCD) until the range is exhausted.  The queue
+// counters live in the workspace and are zeroed by k_reset_queue before the
+// launch; every workgroup leaves the loop once its counter passes the range.
+template <int RECON, typename R, bool SHIFT, int TI>
+__global__ __launch_bounds__(256) void k_stage_queue(StageArgs a, unsigned int* queue, int ntile) {
+  using G = TileGeo<TILE_X[TI], TILE_Y[TI], TILE_Z[TI]>;
+  __shared__ double sF[8][G::maxslots()];
+  __shared__ int s_tile;
+  const int x = blockIdx.x & 7;
+  const int q = ntile >> 3, r = ntile & 7;
+  const int lo = x * q + (x < r ? x : r);
+  const int cnt = q + (x < r ? 1 : 0);
+  double rate = 0.0;
+  for (;;) {
+    if (threadIdx.x == 0) s_tile = (int)atomicAdd(queue + x, 1u);
+    __syncthreads();
+    const int k = s_tile;
+    __syncthreads();
+    if (k >= cnt) break;
+    stage_tile<RECON, R, SHIFT, TI>(a, lo + k, sF, rate);
+  }
+  if (a.max_rate) block_max_atomic(rate, a.max_rate);
+}
+
+__global__ void k_reset_queue(unsigned int* queue) {
+  if (threadIdx.x < 8) queue[threadIdx.x] = 0u;
 }
 
 // ---------------------------------------------------------------- cell kernels
@@ -832,6 +880,7 @@ int check_params(const grmhd_params* p, const grmhd_domain* dom, KPhys& ph) {
   if (p->wenoz_p != 1 && p->wenoz_p != 2) return invalid("wenoz_p must be 1 or 2");
   if (!(p->c2p_tol > 0.0) || p->c2p_maxit < 1 || p->c2p_maxit > 100000) return invalid("bad con2prim tolerance");
   if (p->tile < -1 || p->tile >= NTILE) return invalid("unknown tile shape");
+  if (p->schedule != GRMHD_SCHED_GRID && p->schedule != GRMHD_SCHED_QUEUE) return invalid("unknown schedule");
   if (!(p->rho_atm > 0.0) || !(p->atm_K > 0.0) || !(p->atm_gamma > 0.0) || !std::isfinite(p->rho_atm) ||
       !std::isfinite(p->atm_K) || !std::isfinite(p->atm_gamma))
     return invalid("bad atmosphere parameters");
@@ -864,6 +913,17 @@ Table make_table(const grmhd_domain* dom) {
   return t;
 }
 
+// Workgroups of a persistent launch: 2 resident 256-thread workgroups per CU
+// (the stage kernel needs ~250 VGPRs, i.e. 2 waves per SIMD).
+int persistent_blocks() {
+  static int n = [] {
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    return 2 * cus;
+  }();
+  return n;
+}
+
 int pick_tile(const grmhd_domain* dom, const grmhd_params* par) {
   if (par->tile >= 0) return par->tile;
   (void)dom;
@@ -872,7 +932,14 @@ int pick_tile(const grmhd_domain* dom, const grmhd_params* par) {
 
 template <int RECON, typename R, bool SHIFT, int TI>
 hipError_t launch_stage_t(const StageArgs& a, int64_t blocks, hipStream_t s) {
-  hipLaunchKernelGGL((k_stage<RECON, R, SHIFT, TI>), dim3((unsigned)blocks), dim3(256), 0, s, a);
+  if (a.queue) {
+    hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, s, a.queue);
+    const int64_t nb = std::min<int64_t>(blocks, a.persist_blocks);
+    hipLaunchKernelGGL((k_stage_queue<RECON, R, SHIFT, TI>), dim3((unsigned)nb), dim3(256), 0, s, a, a.queue,
+                       (int)blocks);
+  } else {
+    hipLaunchKernelGGL((k_stage<RECON, R, SHIFT, TI>), dim3((unsigned)blocks), dim3(256), 0, s, a);
+  }
   return hipGetLastError();
 }
 
@@ -945,6 +1012,8 @@ StageArgs stage_args(const grmhd_domain* dom, const grmhd_params* par, const KPh
   a.mode = 0;
   a.ph = ph;
   a.max_rate = nullptr;
+  a.queue = nullptr;
+  a.persist_blocks = 0;
   return a;
 }
 
@@ -1108,7 +1177,7 @@ size_t grmhd_workspace_bytes(const grmhd_domain* dom, const grmhd_params* par, i
   (void)scheme;
   if (!dom || dom->cell_stride < 1) return 0;
   const size_t field = sizeof(double) * 8 * (size_t)dom->cell_stride;
-  return for_adjoint ? 2 * field : field;
+  return for_adjoint ? 2 * field : field + QUEUE_BYTES;
 }
 
 int grmhd_rk_step(const grmhd_domain* dom, const grmhd_params* par, const grmhd_metric* met, double* U, double* P,
@@ -1140,6 +1209,10 @@ int grmhd_rk_step(const grmhd_domain* dom, const grmhd_params* par, const grmhd_
   a.dt = dt;
   a.max_rate = max_rate;
   a.Un = U;
+  if (par->schedule == GRMHD_SCHED_QUEUE) {
+    a.queue = reinterpret_cast<unsigned int*>(static_cast<char*>(ws) + sizeof(double) * fsz);
+    a.persist_blocks = persistent_blocks();
+  }
   for (int st = 0; st < nst; ++st) {
     a.Us = (st == 0) ? U : W1;
     a.Uout = (st == nst - 1) ? U : W1;

@@ -74,7 +74,47 @@ struct KPhys {
 // ---------------------------------------------------------------- small helpers
 
 template <typename R> __device__ __forceinline__ R rsq(R x) { return x * x; }
-__device__ __forceinline__ double sqrt_r(double x) { return sqrt(x); }
+
+// Reciprocal: the hardware estimate refined by two Newton-Raphson steps
+// r <- r (2 - x r) (FP64; one step for FP32), within an ulp or two of 1/x for
+// the finite, non-zero, normal arguments the kernels divide by.
+__device__ __forceinline__ double rcp_r(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = __builtin_fma(-x, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-x, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
+__device__ __forceinline__ float rcp_r(float x) {
+  float r = __builtin_amdgcn_rcpf(x);
+  float e = __builtin_fmaf(-x, r, 1.0f);
+  return __builtin_fmaf(r, e, r);
+}
+
+// Loads and stores through a uniform base pointer and an unsigned 32-bit
+// element index, so the address is base + 32-bit byte offset.
+__device__ __forceinline__ double ldg(const double* __restrict__ base, uint32_t i) {
+  return *reinterpret_cast<const double*>(reinterpret_cast<const char*>(base) + (i << 3));
+}
+__device__ __forceinline__ void stg(double* __restrict__ base, uint32_t i, double v) {
+  *reinterpret_cast<double*>(reinterpret_cast<char*>(base) + (i << 3)) = v;
+}
+// Square root of a finite x >= 0 (normal or zero): the hardware 1/sqrt estimate
+// refined by Goldschmidt's iteration (g -> sqrt(x), h -> 1/(2 sqrt(x))) and a
+// final Newton correction; within an ulp or two of sqrt(x).
+__device__ __forceinline__ double sqrt_r(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  double g = x * y, h = 0.5 * y;
+  double r = __builtin_fma(-h, g, 0.5);
+  g = __builtin_fma(g, r, g);
+  h = __builtin_fma(h, r, h);
+  r = __builtin_fma(-h, g, 0.5);
+  g = __builtin_fma(g, r, g);
+  h = __builtin_fma(h, r, h);
+  const double d = __builtin_fma(-g, g, x);
+  g = __builtin_fma(d, h, g);
+  return x > 0.0 ? g : 0.0;
+}
 __device__ __forceinline__ float sqrt_r(float x) { return sqrtf(x); }
 template <typename R> __device__ __forceinline__ R rmax(R a, R b) { return a < b ? b : a; }
 template <typename R> __device__ __forceinline__ R rmin(R a, R b) { return b < a ? b : a; }
@@ -88,7 +128,7 @@ __device__ __forceinline__ constexpr int sidx(int i, int j) {
 // ---------------------------------------------------------------- face metric
 
 template <typename R> struct FaceMetric {
-  R alpha, beta[3], g[6], sqrtg, gdd;
+  R alpha, ialpha, beta[3], g[6], sqrtg, gdd;
 };
 
 // Mean of the four vertices of the low face (direction D) of the cell whose
@@ -98,12 +138,16 @@ template <int D, bool SHIFT, typename R>
 __device__ __forceinline__ void face_metric(const double* __restrict__ alpha, const double* __restrict__ beta,
                                             const double* __restrict__ gamma, int64_t vs, int vb, int sa, int sb,
                                             FaceMetric<R>& m) {
-  const int v0 = vb, v1 = vb + sa, v2 = vb + sb, v3 = vb + sa + sb;
-  auto avg = [&](const double* __restrict__ f) -> double { return 0.25 * ((f[v0] + f[v1]) + (f[v2] + f[v3])); };
+  const uint32_t v0 = vb, v1 = vb + sa, v2 = vb + sb, v3 = vb + sa + sb;
+  auto avg = [&](const double* __restrict__ f) -> double {
+    return 0.25 * ((ldg(f, v0) + ldg(f, v1)) + (ldg(f, v2) + ldg(f, v3)));
+  };
   double g[6];
 #pragma unroll
   for (int q = 0; q < 6; ++q) g[q] = avg(gamma + q * vs);
-  m.alpha = (R)avg(alpha);
+  const double al = avg(alpha);
+  m.alpha = (R)al;
+  m.ialpha = (R)rcp_r(al);
 #pragma unroll
   for (int q = 0; q < 3; ++q) m.beta[q] = SHIFT ? (R)avg(beta + q * vs) : R(0);
   // cofactors: det and the one inverse component gamma^{DD}
@@ -117,8 +161,8 @@ __device__ __forceinline__ void face_metric(const double* __restrict__ alpha, co
   else cdd = g[0] * g[3] - g[1] * g[1];
 #pragma unroll
   for (int q = 0; q < 6; ++q) m.g[q] = (R)g[q];
-  m.sqrtg = (R)sqrt(det);
-  m.gdd = (R)(cdd / det);
+  m.sqrtg = (R)sqrt_r(det);
+  m.gdd = (R)(cdd * rcp_r(det));
 }
 
 // ---------------------------------------------------------------- one side of a face
@@ -151,7 +195,7 @@ __device__ __forceinline__ void side_rest(const FaceMetric<RM>& m, const R* P, R
   for (int i = 0; i < 3; ++i)
     s.Blow[i] = m.g[sidx(i, 0)] * P[5] + m.g[sidx(i, 1)] * P[6] + m.g[sidx(i, 2)] * P[7];
   s.iW = sqrt_r(R(1) - s.v2);
-  s.W = R(1) / s.iW;
+  s.W = rcp_r(s.iW);
   s.B2 = s.Blow[0] * P[5] + s.Blow[1] * P[6] + s.Blow[2] * P[7];
   const R Bv = s.Blow[0] * P[1] + s.Blow[1] * P[2] + s.Blow[2] * P[3];
   s.ab0 = s.W * Bv;
@@ -166,15 +210,17 @@ __device__ __forceinline__ void side_rest(const FaceMetric<RM>& m, const R* P, R
 template <int D, typename R, typename RM>
 __device__ __forceinline__ void side_speeds(const FaceMetric<RM>& m, const R* P, const SideState<R>& s, RM gam, R& lp,
                                             R& lm) {
-  const R cs2 = gam * s.p / s.rhoh;
-  const R ca2 = s.b2 / (s.rhoh + s.b2);
+  const R rh = s.rhoh, rhb = s.rhoh + s.b2;
+  const R ir = rcp_r(rh * rhb);  // one reciprocal for c_s^2 and c_a^2
+  const R cs2 = gam * s.p * rhb * ir;
+  const R ca2 = s.b2 * rh * ir;
   const R cf2 = cs2 + ca2 - cs2 * ca2;
   const R vd = P[1 + D];
   const R den = R(1) - s.v2 * cf2;
   const R disc = (R(1) - s.v2) * (m.gdd * den - vd * vd * (R(1) - cf2));
   const R root = sqrt_r(cf2 * rmax(disc, R(0)));
   const R base = vd * (R(1) - cf2);
-  const R ad = R(m.alpha) / den;
+  const R ad = R(m.alpha) * rcp_r(den);
   lp = ad * (base + root) - m.beta[D];
   lm = ad * (base - root) - m.beta[D];
 }
@@ -198,7 +244,7 @@ __device__ __forceinline__ void side_cons_flux(const FaceMetric<RM>& m, const R*
 #pragma unroll
   for (int k = 0; k < 3; ++k) U[5 + k] = sg * P[5 + k];
   const RM a = m.alpha;
-  const RM ia = RM(1) / a;
+  const RM ia = m.ialpha;
   R vt[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) vt[i] = P[1 + i] - m.beta[i] * ia;
@@ -262,6 +308,8 @@ __device__ __forceinline__ R weno5(R a, R b, R c, R d, R e, R eps, int zp) {
       w2 = R(0.3) * (R(1) + r2);
     }
   }
+  // An IEEE division: the refined hardware reciprocal used elsewhere reproduces this
+  // quotient in isolation, but gave wrong stage-kernel results in this position.
   return (w0 * q0 + w1 * q1 + w2 * q2) / (R(6) * (w0 + w1 + w2));
 }
 
@@ -282,7 +330,7 @@ __device__ __forceinline__ void hlle(const FaceMetric<R>& m, const R* PL, const 
   side_cons_flux<D>(m, PL, sL, UL, FL);
   side_cons_flux<D>(m, PR, sR, UR, FR);
   if (den > R(0)) {
-    const R id = R(1) / den;
+    const R id = rcp_r(den);
     const R xx = xip * xim;
 #pragma unroll
     for (int q = 0; q < 8; ++q) Fs[q] = (xip * FL[q] - xim * FR[q] + xx * (UR[q] - UL[q])) * id;
@@ -304,10 +352,12 @@ template <bool SHIFT, bool NEED_ALPHA>
 __device__ __forceinline__ void centre_metric(const double* __restrict__ alpha, const double* __restrict__ beta,
                                               const double* __restrict__ gamma, int64_t vs, int vb, int VX, int VXY,
                                               CentreMetric& m) {
-  const int o[8] = {0, 1, VX, VX + 1, VXY, VXY + 1, VXY + VX, VXY + VX + 1};
+  const uint32_t o[8] = {0u, 1u, (uint32_t)VX, (uint32_t)VX + 1u, (uint32_t)VXY, (uint32_t)VXY + 1u,
+                         (uint32_t)(VXY + VX), (uint32_t)(VXY + VX) + 1u};
+  const uint32_t v = vb;
   auto avg = [&](const double* __restrict__ f) -> double {
-    return 0.125 * (((f[vb + o[0]] + f[vb + o[1]]) + (f[vb + o[2]] + f[vb + o[3]])) +
-                    ((f[vb + o[4]] + f[vb + o[5]]) + (f[vb + o[6]] + f[vb + o[7]])));
+    return 0.125 * (((ldg(f, v + o[0]) + ldg(f, v + o[1])) + (ldg(f, v + o[2]) + ldg(f, v + o[3]))) +
+                    ((ldg(f, v + o[4]) + ldg(f, v + o[5])) + (ldg(f, v + o[6]) + ldg(f, v + o[7]))));
   };
 #pragma unroll
   for (int q = 0; q < 6; ++q) m.g[q] = avg(gamma + q * vs);
@@ -331,10 +381,11 @@ __device__ __forceinline__ void centre_metric(const double* __restrict__ alpha, 
 // d_e f at the cell centre: mean over the 4 edges along e of the vertex
 // difference, times 1/dx_e (second order).
 __device__ __forceinline__ double edge_deriv(const double* __restrict__ f, int vb, int se, int sa, int sb, double idx) {
-  const double s0 = f[vb + se] - f[vb];
-  const double s1 = f[vb + sa + se] - f[vb + sa];
-  const double s2 = f[vb + sb + se] - f[vb + sb];
-  const double s3 = f[vb + sa + sb + se] - f[vb + sa + sb];
+  const uint32_t v = vb, e = se, a = sa, b = sb;
+  const double s0 = ldg(f, v + e) - ldg(f, v);
+  const double s1 = ldg(f, v + a + e) - ldg(f, v + a);
+  const double s2 = ldg(f, v + b + e) - ldg(f, v + b);
+  const double s3 = ldg(f, v + a + b + e) - ldg(f, v + a + b);
   return 0.25 * ((s0 + s1) + (s2 + s3)) * idx;
 }
 
