@@ -33,6 +33,7 @@ WORKLOADS = {
     "curved256": dict(kind="config1", n=256, desc="static curved metric 256^3, WENO5, HLLE, FP64, SSPRK3"),
     "flat64": dict(kind="config0", n=64, desc="flat 64^3 with jump, minmod, HLLE, FP64, SSPRK3"),
     "curved384-mixed": dict(kind="config3", n=384, desc="static curved metric 384^3, WENO5, FP32 recon+HLLE"),
+    "curved256-mixed": dict(kind="config3", n=256, desc="static curved metric 256^3, WENO5, FP32 recon+HLLE"),
     "curved384-fp64": dict(kind="config3-fp64", n=384,
                            desc="static curved metric 384^3 (mixed-precision recipe and seed), WENO5, HLLE, FP64"),
     "batched400": dict(kind="config2", n=0, desc="400 uneven boxes (edges 16..64, flat/curved), WENO5, FP64"),

@@ -30,6 +30,9 @@ using namespace gk;
 namespace {
 
 constexpr uint64_t TABLE_MAGIC = 0x47524d4844544231ull;  // "GRMHDTB1"
+// Stage-kernel reconstruction codes: the public ones, plus WENO-Z with exponent 2
+// (the exponent is a compile-time constant of each stage-kernel instance).
+constexpr int RECON_WENOZ2 = GRMHD_RECON_WENOZ + 1;
 constexpr size_t QUEUE_BYTES = 256;  // per-XCD tile-queue counters at the end of the step workspace
 
 // tile shapes of the stage kernel (TX * TY * TZ = 256)
@@ -92,11 +95,12 @@ __device__ __forceinline__ int xcd_tile(int blk, int n) {
   return x * q + (x < r ? x : r) + m;
 }
 
-template <int D, int RECON, typename R, bool SHIFT>
+// Flux through the low face (direction D) of cell (i, j, k); the face's 4
+// vertices are read through vt at vb, vb + sa, vb + sb, vb + sa + sb.
+template <int D, int RECON, typename R, bool SHIFT, typename V>
 __device__ __forceinline__ void face_flux(const StageArgs& a, const KBox& bx, const double* __restrict__ Pb,
-                                          const double* __restrict__ alb, const double* __restrict__ beb,
-                                          const double* __restrict__ gab, int i, int j, int k, double F[8],
-                                          double& rate) {
+                                          const V& vt, uint32_t vb, uint32_t sa, uint32_t sb, int i, int j, int k,
+                                          double F[8], double& rate) {
   const int ng = bx.ng;
   const int c = (D == 0) ? i : (D == 1 ? j : k);
   const int nD = bx.n[D];
@@ -125,24 +129,20 @@ __device__ __forceinline__ void face_flux(const StageArgs& a, const KBox& bx, co
       PL[q] = s[2] + R(0.5) * minmod(s[2] - s[1], s[3] - s[2]);
       PR[q] = s[3] - R(0.5) * minmod(s[3] - s[2], s[4] - s[3]);
     } else {
-      const bool z = (RECON == GRMHD_RECON_WENOZ);
+      constexpr bool z = (RECON >= GRMHD_RECON_WENOZ);
+      constexpr int zp = (RECON == RECON_WENOZ2) ? 2 : 1;
       const R eps = (R)(z ? a.ph.wenoz_eps : a.ph.weno_eps);
       if (z) {
-        PL[q] = weno5<true>(s[0], s[1], s[2], s[3], s[4], eps, a.ph.wenoz_p);
-        PR[q] = weno5<true>(s[5], s[4], s[3], s[2], s[1], eps, a.ph.wenoz_p);
+        PL[q] = weno5<true, zp>(s[0], s[1], s[2], s[3], s[4], eps, zp);
+        PR[q] = weno5<true, zp>(s[5], s[4], s[3], s[2], s[1], eps, zp);
       } else {
         PL[q] = weno5<false>(s[0], s[1], s[2], s[3], s[4], eps, 1);
         PR[q] = weno5<false>(s[5], s[4], s[3], s[2], s[1], eps, 1);
       }
     }
   }
-  // face metric from the 4 vertices of the face
-  const int vb = ((k + ng) * (bx.VXY / bx.VX) + (j + ng)) * bx.VX + (i + ng);
-  constexpr int A = (D + 1) % 3, B = (D + 2) % 3;
-  const int sa = (A == 0) ? 1 : (A == 1 ? bx.VX : bx.VXY);
-  const int sb = (B == 0) ? 1 : (B == 1 ? bx.VX : bx.VXY);
   FaceMetric<R> m;
-  face_metric<D, SHIFT, R>(alb, beb, gab, a.vs, vb, sa, sb, m);
+  face_metric<D, SHIFT, R>(vt, vb, sa, sb, m);
   // positivity: fall back to the cell values on a side that is not physical
   SideState<R> sL, sR;
   side_v2(m, PL, sL);
@@ -175,14 +175,16 @@ template <int TX, int TY, int TZ> struct TileGeo {
   static constexpr int maxslots() {
     return std::max(slots(0), std::max(slots(1), slots(2)));
   }
+  // the tile's vertex block: vertices org .. org + T along each axis
+  static constexpr int VBX = TX + 1, VBY = TY + 1, VBZ = TZ + 1, NVB = VBX * VBY * VBZ;
+  static constexpr int nvf(bool shift) { return shift ? 10 : 7; }
 };
 
 template <int D, int RECON, typename R, bool SHIFT, int TX, int TY, int TZ>
 __device__ __forceinline__ void direction_phase(const StageArgs& a, const KBox& bx, const double* __restrict__ Pb,
-                                                const double* __restrict__ alb, const double* __restrict__ beb,
-                                                const double* __restrict__ gab, const int org[3], const int l[3],
-                                                bool valid, double (*sF)[TileGeo<TX, TY, TZ>::maxslots()],
-                                                double acc[8], double& rate) {
+                                                const double* sV, const int org[3], const int l[3], bool valid,
+                                                double (*sF)[TileGeo<TX, TY, TZ>::maxslots()], double acc[8],
+                                                double& rate) {
   using G = TileGeo<TX, TY, TZ>;
   constexpr int SX = G::SX[D], SY = G::SY[D];
   constexpr int T_D = (D == 0) ? TX : (D == 1 ? TY : TZ);
@@ -209,8 +211,10 @@ __device__ __forceinline__ void direction_phase(const StageArgs& a, const KBox& 
     }
     if (ok) {
       double F[8];
-      face_flux<D, RECON, R, SHIFT>(a, bx, Pb, alb, beb, gab, org[0] + fl[0], org[1] + fl[1], org[2] + fl[2], F,
-                                    rate);
+      constexpr uint32_t VS[3] = {1u, (uint32_t)G::VBX, (uint32_t)(G::VBX * G::VBY)};
+      const uint32_t lv = fl[0] + G::VBX * (fl[1] + G::VBY * fl[2]);
+      face_flux<D, RECON, R, SHIFT>(a, bx, Pb, LdsVerts<G::NVB>{sV}, lv, VS[(D + 1) % 3], VS[(D + 2) % 3],
+                                    org[0] + fl[0], org[1] + fl[1], org[2] + fl[2], F, rate);
       const int slot = fl[0] + SX * (fl[1] + SY * fl[2]);
 #pragma unroll
       for (int q = 0; q < 8; ++q) sF[q][slot] = F[q];
@@ -230,8 +234,9 @@ __device__ __forceinline__ void direction_phase(const StageArgs& a, const KBox& 
 template <int RECON, typename R, bool SHIFT, int TI>
 __device__ __forceinline__ void stage_tile(const StageArgs& a, int tg,
                                            double (*sF)[TileGeo<TILE_X[TI], TILE_Y[TI], TILE_Z[TI]>::maxslots()],
-                                           double& rate) {
+                                           double* sV, double& rate) {
   constexpr int TX = TILE_X[TI], TY = TILE_Y[TI], TZ = TILE_Z[TI];
+  using G = TileGeo<TX, TY, TZ>;
   const int b = find_box(a.tab.tile_prefix + TI * (a.tab.nbox + 1), a.tab.nbox, tg);
   const KBox& bx = a.tab.box[b];
   const int t = tg - a.tab.tile_prefix[TI * (a.tab.nbox + 1) + b];
@@ -242,23 +247,38 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int tg,
   const int i = org[0] + l[0], j = org[1] + l[1], k = org[2] + l[2];
   const bool valid = (i < bx.n[0]) && (j < bx.n[1]) && (k < bx.n[2]);
   const double* __restrict__ Pb = a.P + bx.cell_off;
-  const double* __restrict__ alb = a.alpha + bx.vert_off;
-  const double* __restrict__ beb = SHIFT ? a.beta + bx.vert_off : nullptr;
-  const double* __restrict__ gab = a.gamma + bx.vert_off;
+  // Stage the tile's vertex metric in LDS: every face and cell of the tile reads
+  // its vertices from this block.  Vertices past the box's last interior vertex
+  // plane are not loaded (no valid cell or face of the tile reads them).
+  {
+    const GlobalVerts gv{a.alpha + bx.vert_off, SHIFT ? a.beta + bx.vert_off : nullptr, a.gamma + bx.vert_off,
+                         a.vs};
+    const int ng = bx.ng, VY = bx.VXY / bx.VX;
+    for (int e = tid; e < G::NVB; e += 256) {
+      const int vx = e % G::VBX, vy = (e / G::VBX) % G::VBY, vz = e / (G::VBX * G::VBY);
+      if (org[0] + vx <= bx.n[0] && org[1] + vy <= bx.n[1] && org[2] + vz <= bx.n[2]) {
+        const uint32_t v = ((org[2] + vz + ng) * VY + (org[1] + vy + ng)) * bx.VX + (org[0] + vx + ng);
+#pragma unroll
+        for (int f = 0; f < G::nvf(SHIFT); ++f) sV[f * G::NVB + e] = gv(f, v);
+      }
+    }
+  }
+  __syncthreads();
   double acc[8];
 #pragma unroll
   for (int q = 0; q < 8; ++q) acc[q] = 0.0;
-  direction_phase<0, RECON, R, SHIFT, TX, TY, TZ>(a, bx, Pb, alb, beb, gab, org, l, valid, sF, acc, rate);
-  direction_phase<1, RECON, R, SHIFT, TX, TY, TZ>(a, bx, Pb, alb, beb, gab, org, l, valid, sF, acc, rate);
-  direction_phase<2, RECON, R, SHIFT, TX, TY, TZ>(a, bx, Pb, alb, beb, gab, org, l, valid, sF, acc, rate);
+  direction_phase<0, RECON, R, SHIFT, TX, TY, TZ>(a, bx, Pb, sV, org, l, valid, sF, acc, rate);
+  direction_phase<1, RECON, R, SHIFT, TX, TY, TZ>(a, bx, Pb, sV, org, l, valid, sF, acc, rate);
+  direction_phase<2, RECON, R, SHIFT, TX, TY, TZ>(a, bx, Pb, sV, org, l, valid, sF, acc, rate);
   if (valid) {
     const int ng = bx.ng;
     const int c = ((k + ng) * (bx.NXY / bx.NX) + (j + ng)) * bx.NX + (i + ng);
-    const int vb = ((k + ng) * (bx.VXY / bx.VX) + (j + ng)) * bx.VX + (i + ng);
+    const uint32_t lv = l[0] + G::VBX * (l[1] + G::VBY * l[2]);
+    const LdsVerts<G::NVB> vt{sV};
     CentreMetric cm;
-    centre_metric<SHIFT, true>(alb, beb, gab, a.vs, vb, bx.VX, bx.VXY, cm);
+    centre_metric<SHIFT, true>(vt, lv, G::VBX, G::VBX * G::VBY, cm);
     MetricDeriv md;
-    metric_deriv<SHIFT>(alb, beb, gab, a.vs, vb, bx.VX, bx.VXY, bx.inv_dx, md);
+    metric_deriv<SHIFT>(vt, lv, G::VBX, G::VBX * G::VBY, bx.inv_dx, md);
     double P[8], S[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) P[q] = ldg(Pb + q * a.cs, (uint32_t)c);
@@ -280,11 +300,12 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int tg,
 // One workgroup per tile.  Workgroups are dispatched round-robin over the 8
 // XCDs; each XCD gets a contiguous run of tiles so tiles sharing halos share an L2.
 template <int RECON, typename R, bool SHIFT, int TI>
-__global__ __launch_bounds__(256) void k_stage(StageArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_stage(StageArgs a) {
   using G = TileGeo<TILE_X[TI], TILE_Y[TI], TILE_Z[TI]>;
   __shared__ double sF[8][G::maxslots()];
+  __shared__ double sV[G::nvf(SHIFT) * G::NVB];
   double rate = 0.0;
-  stage_tile<RECON, R, SHIFT, TI>(a, xcd_tile(blockIdx.x, gridDim.x), sF, rate);
+  stage_tile<RECON, R, SHIFT, TI>(a, xcd_tile(blockIdx.x, gridDim.x), sF, sV, rate);
   if (a.max_rate) block_max_atomic(rate, a.max_rate);
 }
 
@@ -293,9 +314,10 @@ __global__ __launch_bounds__(256) void k_stage(StageArgs a) {
 // counters live in the workspace and are zeroed by k_reset_queue before the
 // launch; every workgroup leaves the loop once its counter passes the range.
 template <int RECON, typename R, bool SHIFT, int TI>
-__global__ __launch_bounds__(256) void k_stage_queue(StageArgs a, unsigned int* queue, int ntile) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_stage_queue(StageArgs a, unsigned int* queue, int ntile) {
   using G = TileGeo<TILE_X[TI], TILE_Y[TI], TILE_Z[TI]>;
   __shared__ double sF[8][G::maxslots()];
+  __shared__ double sV[G::nvf(SHIFT) * G::NVB];
   __shared__ int s_tile;
   const int x = blockIdx.x & 7;
   const int q = ntile >> 3, r = ntile & 7;
@@ -308,7 +330,7 @@ __global__ __launch_bounds__(256) void k_stage_queue(StageArgs a, unsigned int* 
     const int k = s_tile;
     __syncthreads();
     if (k >= cnt) break;
-    stage_tile<RECON, R, SHIFT, TI>(a, lo + k, sF, rate);
+    stage_tile<RECON, R, SHIFT, TI>(a, lo + k, sF, sV, rate);
   }
   if (a.max_rate) block_max_atomic(rate, a.max_rate);
 }
@@ -341,7 +363,7 @@ __global__ __launch_bounds__(C2P_BLOCK) void k_con2prim(CellArgs a) {
   if (cell_of(a.tab, blockIdx.x, threadIdx.x, b, c, vb)) {
     const KBox& bx = a.tab.box[b];
     CentreMetric cm;
-    centre_metric<false, false>(nullptr, nullptr, a.gamma + bx.vert_off, a.vs, vb, bx.VX, bx.VXY, cm);
+    centre_metric<false, false>(GlobalVerts{nullptr, nullptr, a.gamma + bx.vert_off, a.vs}, vb, bx.VX, bx.VXY, cm);
     const int64_t cc = bx.cell_off + c;
     double U[8], P[8];
 #pragma unroll
@@ -376,7 +398,7 @@ __global__ __launch_bounds__(C2P_BLOCK) void k_prim2con(Table tab, const double*
   if (!cell_of(tab, blockIdx.x, threadIdx.x, b, c, vb)) return;
   const KBox& bx = tab.box[b];
   CentreMetric cm;
-  centre_metric<false, false>(nullptr, nullptr, gamma + bx.vert_off, vs, vb, bx.VX, bx.VXY, cm);
+  centre_metric<false, false>(GlobalVerts{nullptr, nullptr, gamma + bx.vert_off, vs}, vb, bx.VX, bx.VXY, cm);
   const int64_t cc = bx.cell_off + c;
   double p[8], u[8];
 #pragma unroll
@@ -468,8 +490,9 @@ __global__ __launch_bounds__(256) void k_adj_face(AdjArgs a) {
   const int sa = (A == 0) ? 1 : (A == 1 ? bx.VX : bx.VXY);
   const int sb = (B == 0) ? 1 : (B == 1 ? bx.VX : bx.VXY);
   FaceMetric<double> m;
-  face_metric<D, SHIFT, double>(a.alpha + bx.vert_off, SHIFT ? a.beta + bx.vert_off : nullptr,
-                                a.gamma + bx.vert_off, a.vs, vb, sa, sb, m);
+  face_metric<D, SHIFT, double>(
+      GlobalVerts{a.alpha + bx.vert_off, SHIFT ? a.beta + bx.vert_off : nullptr, a.gamma + bx.vert_off, a.vs}, vb, sa,
+      sb, m);
   SideState<double> sL, sR;
   side_v2(m, PL, sL);
   side_v2(m, PR, sR);
@@ -654,8 +677,8 @@ __global__ __launch_bounds__(C2P_BLOCK) void k_adj_cell(AdjCellArgs a) {
   const KBox& bx = a.tab.box[b];
   const int64_t cc = bx.cell_off + c;
   CentreMetric cm;
-  centre_metric<SHIFT, true>(a.alpha + bx.vert_off, SHIFT ? a.beta + bx.vert_off : nullptr, a.gamma + bx.vert_off,
-                             a.vs, vb, bx.VX, bx.VXY, cm);
+  const GlobalVerts gv{a.alpha + bx.vert_off, SHIFT ? a.beta + bx.vert_off : nullptr, a.gamma + bx.vert_off, a.vs};
+  centre_metric<SHIFT, true>(gv, vb, bx.VX, bx.VXY, cm);
   double P[8], v[8], pb[8];
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
@@ -671,8 +694,7 @@ __global__ __launch_bounds__(C2P_BLOCK) void k_adj_cell(AdjCellArgs a) {
   }
   if (a.mode == 0) {
     MetricDeriv md;
-    metric_deriv<SHIFT>(a.alpha + bx.vert_off, SHIFT ? a.beta + bx.vert_off : nullptr, a.gamma + bx.vert_off, a.vs,
-                        vb, bx.VX, bx.VXY, bx.inv_dx, md);
+    metric_deriv<SHIFT>(gv, vb, bx.VX, bx.VXY, bx.inv_dx, md);
     DN<8> S[8];
     sources_T<SHIFT>(cm, md, Pd, a.ph.gam, S);
 #pragma unroll
@@ -966,7 +988,9 @@ hipError_t launch_stage(const StageArgs& a, int recon, int precision, int64_t bl
   switch (recon) {
     case GRMHD_RECON_MINMOD: return launch_stage_p<GRMHD_RECON_MINMOD>(a, precision, blocks, s);
     case GRMHD_RECON_WENO5: return launch_stage_p<GRMHD_RECON_WENO5>(a, precision, blocks, s);
-    default: return launch_stage_p<GRMHD_RECON_WENOZ>(a, precision, blocks, s);
+    default:
+      return (a.ph.wenoz_p == 2) ? launch_stage_p<RECON_WENOZ2>(a, precision, blocks, s)
+                                 : launch_stage_p<GRMHD_RECON_WENOZ>(a, precision, blocks, s);
   }
 }
 

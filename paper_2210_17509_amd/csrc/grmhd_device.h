@@ -125,6 +125,31 @@ __device__ __forceinline__ constexpr int sidx(int i, int j) {
   return (i == 0) ? j : (i == 1 ? (j == 0 ? 1 : j + 2) : (j == 0 ? 2 : (j == 1 ? 4 : 5)));
 }
 
+// ---------------------------------------------------------------- vertex metric access
+
+// Vertex fields: 0 = alpha, 1..6 = gamma_ij (xx xy xz yy yz zz), 7..9 = beta^i.
+constexpr int VF_ALPHA = 0, VF_GAMMA = 1, VF_BETA = 7;
+
+// The vertex metric of one box in HBM: field f of the vertex with box-local
+// storage index v.
+struct GlobalVerts {
+  const double* __restrict__ alpha;
+  const double* __restrict__ beta;
+  const double* __restrict__ gamma;
+  int64_t vs;
+  __device__ __forceinline__ double operator()(int f, uint32_t v) const {
+    if (f == VF_ALPHA) return ldg(alpha, v);
+    if (f < VF_BETA) return ldg(gamma + (f - VF_GAMMA) * vs, v);
+    return ldg(beta + (f - VF_BETA) * vs, v);
+  }
+};
+
+// A block of vertices staged in LDS: field f of block-local vertex v at s[f * STRIDE + v].
+template <int STRIDE> struct LdsVerts {
+  const double* s;
+  __device__ __forceinline__ double operator()(int f, uint32_t v) const { return s[f * STRIDE + v]; }
+};
+
 // ---------------------------------------------------------------- face metric
 
 template <typename R> struct FaceMetric {
@@ -132,24 +157,21 @@ template <typename R> struct FaceMetric {
 };
 
 // Mean of the four vertices of the low face (direction D) of the cell whose
-// lower corner is vertex vb: the metric is interpolated linearly from the
-// vertices to the face centre (Sec. II C).
-template <int D, bool SHIFT, typename R>
-__device__ __forceinline__ void face_metric(const double* __restrict__ alpha, const double* __restrict__ beta,
-                                            const double* __restrict__ gamma, int64_t vs, int vb, int sa, int sb,
-                                            FaceMetric<R>& m) {
+// lower corner is vertex vb (sa, sb: vertex strides of the two other axes):
+// the metric is interpolated linearly from the vertices to the face centre
+// (Sec. II C).
+template <int D, bool SHIFT, typename R, typename V>
+__device__ __forceinline__ void face_metric(const V& vt, uint32_t vb, uint32_t sa, uint32_t sb, FaceMetric<R>& m) {
   const uint32_t v0 = vb, v1 = vb + sa, v2 = vb + sb, v3 = vb + sa + sb;
-  auto avg = [&](const double* __restrict__ f) -> double {
-    return 0.25 * ((ldg(f, v0) + ldg(f, v1)) + (ldg(f, v2) + ldg(f, v3)));
-  };
+  auto avg = [&](int f) -> double { return 0.25 * ((vt(f, v0) + vt(f, v1)) + (vt(f, v2) + vt(f, v3))); };
   double g[6];
 #pragma unroll
-  for (int q = 0; q < 6; ++q) g[q] = avg(gamma + q * vs);
-  const double al = avg(alpha);
+  for (int q = 0; q < 6; ++q) g[q] = avg(VF_GAMMA + q);
+  const double al = avg(VF_ALPHA);
   m.alpha = (R)al;
   m.ialpha = (R)rcp_r(al);
 #pragma unroll
-  for (int q = 0; q < 3; ++q) m.beta[q] = SHIFT ? (R)avg(beta + q * vs) : R(0);
+  for (int q = 0; q < 3; ++q) m.beta[q] = SHIFT ? (R)avg(VF_BETA + q) : R(0);
   // cofactors: det and the one inverse component gamma^{DD}
   const double cxx = g[3] * g[5] - g[4] * g[4];
   const double cxy = g[2] * g[4] - g[1] * g[5];
@@ -272,8 +294,10 @@ template <typename R> __device__ __forceinline__ R minmod(R a, R b) {
 // [Shu 98]: Jiang-Shu weights d_k / (eps + beta_k)^2 (ZW = false) or Borges
 // WENO-Z weights d_k (1 + (|beta_0 - beta_2| / (beta_k + eps))^p) (ZW = true).
 // The normalisation is folded into a single division.
-template <bool ZW, typename R>
+// ZPC = 1 or 2 fixes the WENO-Z exponent at compile time; ZPC = 0 takes it from zp.
+template <bool ZW, int ZPC = 0, typename R>
 __device__ __forceinline__ R weno5(R a, R b, R c, R d, R e, R eps, int zp) {
+  if (ZPC != 0) zp = ZPC;
   const R q0 = R(2) * a - R(7) * b + R(11) * c;  // x6
   const R q1 = -b + R(5) * c + R(2) * d;
   const R q2 = R(2) * c + R(5) * d - e;
@@ -348,22 +372,19 @@ struct CentreMetric {
 
 // Cell-centre metric: mean of the cell's 8 vertices; inverse and sqrt(gamma)
 // from the averaged gamma_ij.
-template <bool SHIFT, bool NEED_ALPHA>
-__device__ __forceinline__ void centre_metric(const double* __restrict__ alpha, const double* __restrict__ beta,
-                                              const double* __restrict__ gamma, int64_t vs, int vb, int VX, int VXY,
-                                              CentreMetric& m) {
-  const uint32_t o[8] = {0u, 1u, (uint32_t)VX, (uint32_t)VX + 1u, (uint32_t)VXY, (uint32_t)VXY + 1u,
-                         (uint32_t)(VXY + VX), (uint32_t)(VXY + VX) + 1u};
+template <bool SHIFT, bool NEED_ALPHA, typename V>
+__device__ __forceinline__ void centre_metric(const V& vt, uint32_t vb, uint32_t VX, uint32_t VXY, CentreMetric& m) {
+  const uint32_t o[8] = {0u, 1u, VX, VX + 1u, VXY, VXY + 1u, VXY + VX, VXY + VX + 1u};
   const uint32_t v = vb;
-  auto avg = [&](const double* __restrict__ f) -> double {
-    return 0.125 * (((ldg(f, v + o[0]) + ldg(f, v + o[1])) + (ldg(f, v + o[2]) + ldg(f, v + o[3]))) +
-                    ((ldg(f, v + o[4]) + ldg(f, v + o[5])) + (ldg(f, v + o[6]) + ldg(f, v + o[7]))));
+  auto avg = [&](int f) -> double {
+    return 0.125 * (((vt(f, v + o[0]) + vt(f, v + o[1])) + (vt(f, v + o[2]) + vt(f, v + o[3]))) +
+                    ((vt(f, v + o[4]) + vt(f, v + o[5])) + (vt(f, v + o[6]) + vt(f, v + o[7]))));
   };
 #pragma unroll
-  for (int q = 0; q < 6; ++q) m.g[q] = avg(gamma + q * vs);
-  m.alpha = NEED_ALPHA ? avg(alpha) : 1.0;
+  for (int q = 0; q < 6; ++q) m.g[q] = avg(VF_GAMMA + q);
+  m.alpha = NEED_ALPHA ? avg(VF_ALPHA) : 1.0;
 #pragma unroll
-  for (int q = 0; q < 3; ++q) m.beta[q] = SHIFT ? avg(beta + q * vs) : 0.0;
+  for (int q = 0; q < 3; ++q) m.beta[q] = SHIFT ? avg(VF_BETA + q) : 0.0;
   const double* g = m.g;
   const double cxx = g[3] * g[5] - g[4] * g[4];
   const double cxy = g[2] * g[4] - g[1] * g[5];
@@ -380,12 +401,13 @@ __device__ __forceinline__ void centre_metric(const double* __restrict__ alpha, 
 
 // d_e f at the cell centre: mean over the 4 edges along e of the vertex
 // difference, times 1/dx_e (second order).
-__device__ __forceinline__ double edge_deriv(const double* __restrict__ f, int vb, int se, int sa, int sb, double idx) {
-  const uint32_t v = vb, e = se, a = sa, b = sb;
-  const double s0 = ldg(f, v + e) - ldg(f, v);
-  const double s1 = ldg(f, v + a + e) - ldg(f, v + a);
-  const double s2 = ldg(f, v + b + e) - ldg(f, v + b);
-  const double s3 = ldg(f, v + a + b + e) - ldg(f, v + a + b);
+template <typename V>
+__device__ __forceinline__ double edge_deriv(const V& vt, int f, uint32_t v, uint32_t e, uint32_t a, uint32_t b,
+                                             double idx) {
+  const double s0 = vt(f, v + e) - vt(f, v);
+  const double s1 = vt(f, v + a + e) - vt(f, v + a);
+  const double s2 = vt(f, v + b + e) - vt(f, v + b);
+  const double s3 = vt(f, v + a + b + e) - vt(f, v + a + b);
   return 0.25 * ((s0 + s1) + (s2 + s3)) * idx;
 }
 
@@ -394,19 +416,18 @@ struct MetricDeriv {
   double da[3], dg[3][6], db[3][3];
 };
 
-template <bool SHIFT>
-__device__ __forceinline__ void metric_deriv(const double* __restrict__ alpha, const double* __restrict__ beta,
-                                             const double* __restrict__ gamma, int64_t vs, int vb, int VX, int VXY,
+template <bool SHIFT, typename V>
+__device__ __forceinline__ void metric_deriv(const V& vt, uint32_t vb, uint32_t VX, uint32_t VXY,
                                              const double* inv_dx, MetricDeriv& md) {
-  const int st[3] = {1, VX, VXY};
+  const uint32_t st[3] = {1u, VX, VXY};
 #pragma unroll
   for (int e = 0; e < 3; ++e) {
-    const int se = st[e], sa = st[(e + 1) % 3], sb = st[(e + 2) % 3];
-    md.da[e] = edge_deriv(alpha, vb, se, sa, sb, inv_dx[e]);
+    const uint32_t se = st[e], sa = st[(e + 1) % 3], sb = st[(e + 2) % 3];
+    md.da[e] = edge_deriv(vt, VF_ALPHA, vb, se, sa, sb, inv_dx[e]);
 #pragma unroll
-    for (int q = 0; q < 6; ++q) md.dg[e][q] = edge_deriv(gamma + q * vs, vb, se, sa, sb, inv_dx[e]);
+    for (int q = 0; q < 6; ++q) md.dg[e][q] = edge_deriv(vt, VF_GAMMA + q, vb, se, sa, sb, inv_dx[e]);
 #pragma unroll
-    for (int q = 0; q < 3; ++q) md.db[e][q] = SHIFT ? edge_deriv(beta + q * vs, vb, se, sa, sb, inv_dx[e]) : 0.0;
+    for (int q = 0; q < 3; ++q) md.db[e][q] = SHIFT ? edge_deriv(vt, VF_BETA + q, vb, se, sa, sb, inv_dx[e]) : 0.0;
   }
 }
 
