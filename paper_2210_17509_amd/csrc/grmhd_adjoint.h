@@ -112,6 +112,130 @@ template <int N> __device__ __forceinline__ DN<N> sqrt_r(const DN<N>& a) {
   return r;
 }
 
+// ---------------------------------------------------------------- sources
+
+// Reverse of tmunu_T: Pb += d/dP (Tb00 T00 + sum_i Tb0_i T^{0i} + sum_{i<=j} Tbij_ij T^{ij})
+// (symmetric storage: each off-diagonal T^{ij} once).
+__device__ __forceinline__ void tmunu_vjp(const CentreMetric& m, const double* P, double gam, double Tb00,
+                                          const double* Tb0, const double* Tbij, double* Pb) {
+  // forward values, as in tmunu_T
+  double vlow[3], Blow[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    vlow[i] = m.g[sidx(i, 0)] * P[1] + m.g[sidx(i, 1)] * P[2] + m.g[sidx(i, 2)] * P[3];
+    Blow[i] = m.g[sidx(i, 0)] * P[5] + m.g[sidx(i, 1)] * P[6] + m.g[sidx(i, 2)] * P[7];
+  }
+  const double v2 = vlow[0] * P[1] + vlow[1] * P[2] + vlow[2] * P[3];
+  const double iW = sqrt_r(1.0 - v2);
+  const double W = 1.0 / iW;
+  const double B2 = Blow[0] * P[5] + Blow[1] * P[6] + Blow[2] * P[7];
+  const double Bv = Blow[0] * P[1] + Blow[1] * P[2] + Blow[2] * P[3];
+  const double ia = 1.0 / m.alpha, ia2 = ia * ia;
+  const double b0 = W * Bv * ia;
+  const double b2 = B2 * (iW * iW) + Bv * Bv;
+  const double p = (gam - 1.0) * P[0] * P[4];
+  const double rhohs = P[0] * (1.0 + P[4]) + p + b2;
+  const double u0 = W * ia;
+  double u[3], b[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    u[i] = W * (P[1 + i] - m.beta[i] * ia);
+    b[i] = (P[5 + i] + m.alpha * b0 * u[i]) * iW;
+  }
+  // adjoints of rho h*, P*, u^0, u^i, b^0, b^i from T^{mu nu}; A is Tbij as a full
+  // symmetric matrix with the diagonal doubled (d(x_i x_i) = 2 x_i)
+  double A[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) A[i][j] = (i == j) ? 2.0 * Tbij[sidx(i, i)] : Tbij[sidx(i, j)];
+  double rhb = Tb00 * u0 * u0, Psb = -Tb00 * ia2, u0b = 2.0 * Tb00 * rhohs * u0, b0b = -2.0 * Tb00 * b0;
+  double ub[3], bb[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    rhb += Tb0[i] * u0 * u[i];
+    Psb += Tb0[i] * m.beta[i] * ia2;
+    u0b += Tb0[i] * rhohs * u[i];
+    b0b -= Tb0[i] * b[i];
+    ub[i] = Tb0[i] * rhohs * u0;
+    bb[i] = -Tb0[i] * b0;
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+#pragma unroll
+    for (int j = i; j < 3; ++j) {
+      rhb += Tbij[sidx(i, j)] * u[i] * u[j];
+      Psb += Tbij[sidx(i, j)] * (m.gi[sidx(i, j)] - m.beta[i] * m.beta[j] * ia2);
+    }
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      ub[i] += rhohs * A[i][j] * u[j];
+      bb[i] -= A[i][j] * b[j];
+    }
+  }
+  // b^i = (B^i + alpha b^0 u^i) / W
+  double iWb = 0.0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    Pb[5 + i] += bb[i] * iW;
+    b0b += bb[i] * m.alpha * u[i] * iW;
+    ub[i] += bb[i] * m.alpha * b0 * iW;
+    iWb += bb[i] * (P[5 + i] + m.alpha * b0 * u[i]);
+  }
+  // u^i = W (v^i - beta^i / alpha), u^0 = W / alpha
+  double Wb = u0b * ia;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    Wb += ub[i] * (P[1 + i] - m.beta[i] * ia);
+    Pb[1 + i] += ub[i] * W;
+  }
+  // P* = p + b^2 / 2, rho h* = rho (1 + eps) + p + b^2, p = (Gamma - 1) rho eps
+  const double pb = Psb + rhb, b2b = 0.5 * Psb + rhb;
+  Pb[0] += rhb * (1.0 + P[4]) + pb * (gam - 1.0) * P[4];
+  Pb[4] += rhb * P[0] + pb * (gam - 1.0) * P[0];
+  // alpha b^0 = W (B.v), b^2 = B^2 / W^2 + (B.v)^2
+  Wb += b0b * Bv * ia;
+  const double Bvb = b0b * W * ia + 2.0 * b2b * Bv;
+  const double B2b = b2b * iW * iW;
+  iWb += 2.0 * b2b * B2 * iW;
+  // W = 1 / iW, iW = sqrt(1 - v^2)
+  iWb -= Wb * W * W;
+  const double v2b = -0.5 * iWb * W;
+  // v^2 = v.g.v, B^2 = B.g.B, B.v = B.g.v
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    Pb[1 + k] += 2.0 * v2b * vlow[k] + Bvb * Blow[k];
+    Pb[5 + k] += 2.0 * B2b * Blow[k] + Bvb * vlow[k];
+  }
+}
+
+// Pb += (dS/dP)^T v for the source terms (v indexed like U; only the momenta and
+// tau carry sources).  The map T^{mu nu} -> S is linear, so its transpose applied
+// to v comes from one evaluation on dual numbers with a unit tangent per
+// component of T^{mu nu}; the rest is the reverse of tmunu_T.
+template <bool SHIFT>
+__device__ __forceinline__ void sources_vjp(const CentreMetric& m, const MetricDeriv& md, const double* P, double gam,
+                                            const double* v, double* Pb) {
+  DN<10> T00(0.0), T0[3], Tij[6];
+  T00.d[0] = 1.0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    T0[i] = DN<10>(0.0);
+    T0[i].d[1 + i] = 1.0;
+  }
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    Tij[q] = DN<10>(0.0);
+    Tij[q].d[4 + q] = 1.0;
+  }
+  DN<10> S[8];
+  sources_tail<SHIFT>(m, md, T00, T0, Tij, S);
+  double Tb[10];
+#pragma unroll
+  for (int k = 0; k < 10; ++k) Tb[k] = v[1] * S[1].d[k] + v[2] * S[2].d[k] + v[3] * S[3].d[k] + v[4] * S[4].d[k];
+  tmunu_vjp(m, P, gam, Tb[0], Tb + 1, Tb + 4, Pb);
+}
+
 // ---------------------------------------------------------------- reconstruction gradients
 
 // WENO5 value at the right face of c in (a, b, c, d, e) and its gradient with
@@ -119,8 +243,9 @@ template <int N> __device__ __forceinline__ DN<N> sqrt_r(const DN<N>& a) {
 // un-normalised product form (JS: d_k prod_{j != k} (eps + beta_j)^2; Z:
 // d_k (e_k^p + tau^p) prod_{j != k} e_j^p, e = beta + eps, tau = |beta_0 - beta_2|),
 // which normalises to the forward kernel's weights.
-template <bool ZW>
+template <bool ZW, int ZPC = 0>
 __device__ __forceinline__ double weno5_grad(const double* s, double eps, int zp, double g[5]) {
+  if (ZPC != 0) zp = ZPC;  // exponent fixed at compile time
   const double a = s[0], b = s[1], c = s[2], d = s[3], e = s[4];
   const double q[3] = {2 * a - 7 * b + 11 * c, -b + 5 * c + 2 * d, 2 * c + 5 * d - e};
   const double X0 = a - 2 * b + c, Y0 = a - 4 * b + 3 * c;

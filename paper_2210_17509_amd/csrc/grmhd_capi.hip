@@ -297,10 +297,16 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int tg,
   }
 }
 
+// Waves per SIMD each stage-kernel instance is compiled for: FP32 faces fit three
+// (168 VGPRs with a small spill), FP64 faces two.
+template <typename R> struct StageWaves {
+  static constexpr int value = (sizeof(R) == 4) ? 3 : 2;
+};
+
 // One workgroup per tile.  Workgroups are dispatched round-robin over the 8
 // XCDs; each XCD gets a contiguous run of tiles so tiles sharing halos share an L2.
 template <int RECON, typename R, bool SHIFT, int TI>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_stage(StageArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(StageWaves<R>::value))) void k_stage(StageArgs a) {
   using G = TileGeo<TILE_X[TI], TILE_Y[TI], TILE_Z[TI]>;
   __shared__ double sF[8][G::maxslots()];
   __shared__ double sV[G::nvf(SHIFT) * G::NVB];
@@ -314,7 +320,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 // counters live in the workspace and are zeroed by k_reset_queue before the
 // launch; every workgroup leaves the loop once its counter passes the range.
 template <int RECON, typename R, bool SHIFT, int TI>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_stage_queue(StageArgs a, unsigned int* queue, int ntile) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(StageWaves<R>::value))) void k_stage_queue(StageArgs a, unsigned int* queue,
+                                                                                                    int ntile) {
   using G = TileGeo<TILE_X[TI], TILE_Y[TI], TILE_Z[TI]>;
   __shared__ double sF[8][G::maxslots()];
   __shared__ double sV[G::nvf(SHIFT) * G::NVB];
@@ -427,14 +434,17 @@ struct AdjArgs {
 // side states and of the reconstruction, scattered onto the stencil cells of
 // the face (ghost cells map onto the interior cells they copy).
 template <int D, int RECON, bool SHIFT>
-__global__ __launch_bounds__(256) void k_adj_face(AdjArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_adj_face(AdjArgs a) {
   const int nb = a.tab.nbox;
   const int32_t* pre = a.tab.face_prefix + D * (nb + 1);
   const int b = find_box(pre, nb, blockIdx.x);
   const KBox& bx = a.tab.box[b];
   const int nfx = bx.n[0] + (D == 0), nfy = bx.n[1] + (D == 1), nfz = bx.n[2] + (D == 2);
-  const int lin = (blockIdx.x - pre[b]) * FACE_BLOCK + threadIdx.x;
-  if (lin >= nfx * nfy * nfz) return;
+  // Lanes past the box's last face take part (with nothing to add) in the
+  // wave-level exchange of the x faces below.
+  const int lin_raw = (blockIdx.x - pre[b]) * FACE_BLOCK + threadIdx.x;
+  const bool live = lin_raw < nfx * nfy * nfz;
+  const int lin = live ? lin_raw : 0;
   const int i = lin % nfx;
   const int r = lin / nfx;
   const int j = r % nfy;
@@ -464,13 +474,15 @@ __global__ __launch_bounds__(256) void k_adj_face(AdjArgs a) {
   for (int q = 0; q < 8; ++q) {
     const double vr = (c < nD) ? Vb[q * a.cs + idx[3]] : 0.0;
     const double vl = (c >= 1) ? Vb[q * a.cs + idx[2]] : 0.0;
-    Fb[q] = (vr - vl) * id;
+    Fb[q] = live ? (vr - vl) * id : 0.0;
     any = any || (Fb[q] != 0.0);
   }
-  if (!any) return;
+  if (!__any(any)) return;  // the whole wave has nothing to propagate
   // forward reconstruction values
   double PL[8], PR[8];
-  const double eps = (RECON == GRMHD_RECON_WENOZ) ? a.ph.wenoz_eps : a.ph.weno_eps;
+  constexpr bool ZW = (RECON >= GRMHD_RECON_WENOZ);
+  constexpr int ZP = (RECON == RECON_WENOZ2) ? 2 : 1;
+  const double eps = ZW ? a.ph.wenoz_eps : a.ph.weno_eps;
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
     const double* __restrict__ f = Pb + q * a.cs;
@@ -481,8 +493,8 @@ __global__ __launch_bounds__(256) void k_adj_face(AdjArgs a) {
       PL[q] = s[2] + 0.5 * minmod(s[2] - s[1], s[3] - s[2]);
       PR[q] = s[3] - 0.5 * minmod(s[3] - s[2], s[4] - s[3]);
     } else {
-      PL[q] = weno5<RECON == GRMHD_RECON_WENOZ>(s[0], s[1], s[2], s[3], s[4], eps, a.ph.wenoz_p);
-      PR[q] = weno5<RECON == GRMHD_RECON_WENOZ>(s[5], s[4], s[3], s[2], s[1], eps, a.ph.wenoz_p);
+      PL[q] = weno5<ZW, ZP>(s[0], s[1], s[2], s[3], s[4], eps, ZP);
+      PR[q] = weno5<ZW, ZP>(s[5], s[4], s[3], s[2], s[1], eps, ZP);
     }
   }
   const int vb = ((k + ng) * (bx.VXY / bx.VX) + (j + ng)) * bx.VX + (i + ng);
@@ -554,8 +566,22 @@ __global__ __launch_bounds__(256) void k_adj_face(AdjArgs a) {
   for (int q = 0; q < 8; ++q) qbL[q] = qbR[q] = 0.0;
   side_vjp<D>(m, PL, gam, gm1, gUL, gFL, ip == 1 ? xbp : 0.0, im == 1 ? xbm : 0.0, qbL);
   side_vjp<D>(m, PR, gam, gm1, gUR, gFR, ip == 2 ? xbp : 0.0, im == 2 ? xbm : 0.0, qbR);
-  // reverse of the reconstruction, scattered onto the stencil cells
+  // x faces: a wave holds consecutive faces of one grid line, so the lane of the
+  // face just below cell m (the cell's "owner") gathers the contributions of its
+  // neighbour lanes to m and adds them with one atomic.  give[o]: stencil cell o
+  // is an interior cell whose owner is in this wave; take[o]: this lane's own
+  // cell receives contribution o of lane + 3 - o.
+  const int lane = threadIdx.x & 63;
+  bool give[6], take[6];
 #pragma unroll
+  for (int o = 0; o < 6; ++o) {
+    const int m = c + o - 3, owner = lane + o - 3, from = lane + 3 - o, fc = c + 3 - o;
+    give[o] = (D == 0) && live && m >= 0 && m < nD && owner >= 0 && owner < 64;
+    take[o] = (D == 0) && live && c < nD && from >= 0 && from < 64 && fc >= 0 && fc <= nD;
+  }
+  // reverse of the reconstruction, scattered onto the stencil cells (one field at
+  // a time: only one stencil is live)
+#pragma clang loop unroll(disable)
   for (int q = 0; q < 8; ++q) {
     const double* __restrict__ f = Pb + q * a.cs;
     double sb[6] = {0, 0, 0, 0, 0, 0};
@@ -579,32 +605,44 @@ __global__ __launch_bounds__(256) void k_adj_face(AdjArgs a) {
       double g5[5];
       if (fbL) sb[2] += qbL[q];
       else {
-        weno5_grad<RECON == GRMHD_RECON_WENOZ>(s, eps, a.ph.wenoz_p, g5);
+        weno5_grad<ZW, ZP>(s, eps, ZP, g5);
 #pragma unroll
         for (int o = 0; o < 5; ++o) sb[o] += qbL[q] * g5[o];
       }
       if (fbR) sb[3] += qbR[q];
       else {
         const double sr[5] = {s[5], s[4], s[3], s[2], s[1]};
-        weno5_grad<RECON == GRMHD_RECON_WENOZ>(sr, eps, a.ph.wenoz_p, g5);
+        weno5_grad<ZW, ZP>(sr, eps, ZP, g5);
 #pragma unroll
         for (int o = 0; o < 5; ++o) sb[5 - o] += qbR[q] * g5[o];
       }
     }
+    if (D == 0) {
+      double own = 0.0;
 #pragma unroll
-    for (int o = 0; o < 6; ++o)
-      if (sb[o] != 0.0) unsafeAtomicAdd(Gb + q * a.cs + idx[o], sb[o]);
+      for (int o = 0; o < 6; ++o) {
+        const double x = __shfl(sb[o], (lane + 3 - o) & 63);
+        if (take[o]) own += x;
+        if (!give[o] && sb[o] != 0.0) unsafeAtomicAdd(Gb + q * a.cs + idx[o], sb[o]);
+      }
+      if (own != 0.0) unsafeAtomicAdd(Gb + q * a.cs + idx[3], own);
+    } else {
+#pragma unroll
+      for (int o = 0; o < 6; ++o)
+        if (sb[o] != 0.0) unsafeAtomicAdd(Gb + q * a.cs + idx[o], sb[o]);
+    }
   }
 }
 
 // Solve A^T x = y for the 8x8 Jacobian A = dU/dP of Eqs. (p2c1)-(p2c4); A has
 // the block form [[A11, A12], [0, sqrt(g) I3]] (U_B = sqrt(g) B).
-__device__ __forceinline__ void solve_dUdP_T(const DN<8>* U, double sqrtg, const double* y, double* x) {
+// J[r][c] = dU_r/dP_c for the first five rows.
+__device__ __forceinline__ void solve_dUdP_T(const double (*J)[8], double sqrtg, const double* y, double* x) {
   double M[5][6];  // A11^T | rhs
 #pragma unroll
   for (int r = 0; r < 5; ++r) {
 #pragma unroll
-    for (int cc = 0; cc < 5; ++cc) M[r][cc] = U[cc].d[r];
+    for (int cc = 0; cc < 5; ++cc) M[r][cc] = J[cc][r];
     M[r][5] = y[r];
   }
   // Gaussian elimination with partial pivoting
@@ -646,7 +684,7 @@ __device__ __forceinline__ void solve_dUdP_T(const DN<8>* U, double sqrtg, const
   for (int kk = 0; kk < 3; ++kk) {
     double t = y[5 + kk];
 #pragma unroll
-    for (int q = 0; q < 5; ++q) t -= U[q].d[5 + kk] * x[q];
+    for (int q = 0; q < 5; ++q) t -= J[q][5 + kk] * x[q];
     x[5 + kk] = t * is;
   }
 }
@@ -671,7 +709,7 @@ struct AdjCellArgs {
 // function theorem, and the transposed stage combine
 // U_{s+1} = (1 - c) U^n + c U_s + c dt L(U_s).
 template <bool SHIFT>
-__global__ __launch_bounds__(C2P_BLOCK) void k_adj_cell(AdjCellArgs a) {
+__global__ __launch_bounds__(C2P_BLOCK) __attribute__((amdgpu_waves_per_eu(2))) void k_adj_cell(AdjCellArgs a) {
   int b, c, vb;
   if (!cell_of(a.tab, blockIdx.x, threadIdx.x, b, c, vb)) return;
   const KBox& bx = a.tab.box[b];
@@ -686,26 +724,35 @@ __global__ __launch_bounds__(C2P_BLOCK) void k_adj_cell(AdjCellArgs a) {
     v[q] = a.V[q * a.cs + cc];
     pb[q] = (a.mode == 0) ? a.Pbar[q * a.cs + cc] : v[q];
   }
-  DN<8> Pd[8];
-#pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    Pd[q] = DN<8>(P[q]);
-    Pd[q].d[q] = 1.0;
-  }
+  // (dS/dP)^T v by reverse mode, then dU/dP by forward-mode dual numbers, one
+  // tangent (primitive) per pass; the passes are real loop iterations so only
+  // one pass's dual numbers are live at a time (two waves per SIMD fit).
   if (a.mode == 0) {
     MetricDeriv md;
     metric_deriv<SHIFT>(gv, vb, bx.VX, bx.VXY, bx.inv_dx, md);
-    DN<8> S[8];
-    sources_T<SHIFT>(cm, md, Pd, a.ph.gam, S);
-#pragma unroll
-    for (int q = 1; q < 5; ++q)
-#pragma unroll
-      for (int kk = 0; kk < 8; ++kk) pb[kk] += v[q] * S[q].d[kk];
+    sources_vjp<SHIFT>(cm, md, P, a.ph.gam, v, pb);
   }
-  DN<8> U[8];
-  p2c_cell(cm.g, cm.sqrtg, a.ph.gm1, Pd, U);
+  constexpr int NU = 1;
+  double J[5][8];
+#pragma clang loop unroll(disable)
+  for (int h = 0; h < 8 / NU; ++h) {
+    DN<NU> Pd[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      Pd[q] = DN<NU>(P[q]);
+#pragma unroll
+      for (int t = 0; t < NU; ++t) Pd[q].d[t] = (q == NU * h + t) ? 1.0 : 0.0;
+    }
+    DN<NU> U[8];
+    p2c_cell(cm.g, cm.sqrtg, a.ph.gm1, Pd, U);
+#pragma unroll
+    for (int r = 0; r < 5; ++r)
+#pragma unroll
+      for (int c = 0; c < 8; ++c)
+        if (c / NU == h) J[r][c] = U[r].d[c % NU];
+  }
   double w[8];
-  solve_dUdP_T(U, cm.sqrtg, pb, w);
+  solve_dUdP_T(J, cm.sqrtg, pb, w);
   if (a.mode == 1) {
 #pragma unroll
     for (int q = 0; q < 8; ++q) a.Gn[q * a.cs + cc] = w[q];
@@ -1058,6 +1105,8 @@ hipError_t launch_adj_faces_r(const AdjArgs& a, int recon, const Prepared& pr, h
     case GRMHD_RECON_WENO5:
       return sh ? launch_adj_faces<GRMHD_RECON_WENO5, true>(a, pr, s) : launch_adj_faces<GRMHD_RECON_WENO5, false>(a, pr, s);
     default:
+      if (a.ph.wenoz_p == 2)
+        return sh ? launch_adj_faces<RECON_WENOZ2, true>(a, pr, s) : launch_adj_faces<RECON_WENOZ2, false>(a, pr, s);
       return sh ? launch_adj_faces<GRMHD_RECON_WENOZ, true>(a, pr, s) : launch_adj_faces<GRMHD_RECON_WENOZ, false>(a, pr, s);
   }
 }

@@ -431,19 +431,11 @@ __device__ __forceinline__ void metric_deriv(const V& vt, uint32_t vb, uint32_t 
   }
 }
 
-// Static-metric source terms of Eq. (definition-of-source) in 3+1 form:
-//   S_Sj  = alpha sqrt(g) [T^00 (beta^i beta^k d_j g_ik / 2 - alpha d_j alpha)
-//           + T^0i beta^k d_j g_ik + T^0_i d_j beta^i + T^ik d_j g_ik / 2]
-//   S_tau = alpha sqrt(g) [T^00 (beta^i beta^j K_ij - beta^i d_i alpha)
-//           + T^0i (2 beta^j K_ij - d_i alpha) + T^ij K_ij]
-// with K_ij = (gamma_jk d_i beta^k + gamma_ik d_j beta^k + beta^k d_k gamma_ij) / (2 alpha)
-// for a time-independent slice; S_D = S_B = 0.  T = double, or a dual number
-// for the adjoint.
-template <bool SHIFT, typename T>
-__device__ __forceinline__ void sources_T(const CentreMetric& m, const MetricDeriv& md, const T* P, double gam,
-                                          T S[8]) {
-  const double* da = md.da;
-  // 4-velocity, magnetic 4-vector and T^{mu nu} (Eq. (mhd-stress-energy-tensor))
+// T^{mu nu} of Eq. (mhd-stress-energy-tensor) at a cell centre from the
+// 4-velocity and the magnetic 4-vector: T00, T^{0i} and T^{ij} (symmetric
+// storage).  T = double, or a dual number.
+template <typename T>
+__device__ __forceinline__ void tmunu_T(const CentreMetric& m, const T* P, double gam, T& T00, T T0[3], T Tij[6]) {
   T vlow[3], Blow[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
@@ -469,8 +461,7 @@ __device__ __forceinline__ void sources_T(const CentreMetric& m, const MetricDer
     b[i] = (P[5 + i] + m.alpha * b0 * u[i]) * iW;
   }
   const double ia2 = ia * ia;
-  const T T00 = rhohs * u0 * u0 - Ps * ia2 - b0 * b0;
-  T T0[3], Tij[6];
+  T00 = rhohs * u0 * u0 - Ps * ia2 - b0 * b0;
 #pragma unroll
   for (int i = 0; i < 3; ++i) T0[i] = rhohs * u0 * u[i] + Ps * (m.beta[i] * ia2) - b0 * b[i];
 #pragma unroll
@@ -478,6 +469,21 @@ __device__ __forceinline__ void sources_T(const CentreMetric& m, const MetricDer
 #pragma unroll
     for (int j = i; j < 3; ++j)
       Tij[sidx(i, j)] = rhohs * u[i] * u[j] + Ps * (m.gi[sidx(i, j)] - m.beta[i] * m.beta[j] * ia2) - b[i] * b[j];
+}
+
+// Static-metric source terms of Eq. (definition-of-source) in 3+1 form:
+//   S_Sj  = alpha sqrt(g) [T^00 (beta^i beta^k d_j g_ik / 2 - alpha d_j alpha)
+//           + T^0i beta^k d_j g_ik + T^0_i d_j beta^i + T^ik d_j g_ik / 2]
+//   S_tau = alpha sqrt(g) [T^00 (beta^i beta^j K_ij - beta^i d_i alpha)
+//           + T^0i (2 beta^j K_ij - d_i alpha) + T^ij K_ij]
+// with K_ij = (gamma_jk d_i beta^k + gamma_ik d_j beta^k + beta^k d_k gamma_ij) / (2 alpha)
+// for a time-independent slice; S_D = S_B = 0.  The sources are linear in
+// T^{mu nu} for a fixed metric.  T = double, or a dual number for the adjoint.
+template <bool SHIFT, typename T>
+__device__ __forceinline__ void sources_tail(const CentreMetric& m, const MetricDeriv& md, const T& T00, const T* T0,
+                                             const T* Tij, T S[8]) {
+  const double* da = md.da;
+  const double ia = 1.0 / m.alpha;
   const double as = m.alpha * m.sqrtg;
   S[0] = T(0.0);
   S[5] = S[6] = S[7] = T(0.0);
@@ -546,6 +552,14 @@ __device__ __forceinline__ void sources_T(const CentreMetric& m, const MetricDer
     }
     S[4] = as * (T00 * (bbK - bda) + t0i + tK);
   }
+}
+
+template <bool SHIFT, typename T>
+__device__ __forceinline__ void sources_T(const CentreMetric& m, const MetricDeriv& md, const T* P, double gam,
+                                          T S[8]) {
+  T T00, T0[3], Tij[6];
+  tmunu_T(m, P, gam, T00, T0, Tij);
+  sources_tail<SHIFT>(m, md, T00, T0, Tij, S);
 }
 
 // ---------------------------------------------------------------- prim -> cons at a cell
