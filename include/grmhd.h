@@ -63,8 +63,9 @@ enum { GRMHD_RECON_MINMOD = 0, GRMHD_RECON_WENO5 = 1, GRMHD_RECON_WENOZ = 2 };
 enum { GRMHD_FP64 = 0, GRMHD_MIXED = 1 };
 /* SSPRK3 (Shu-Osher) and SSPRK2 (Heun), written U_{s+1} = U^n + c_s ((U_s - U^n) + dt L(U_s)). */
 enum { GRMHD_SSPRK3 = 0, GRMHD_SSPRK2 = 1 };
-/* Stage-kernel tiles (cells per workgroup, x * y * z = 256): 0 = 16x4x4, 1 = 8x8x4, 2 = 64x2x2. */
-#define GRMHD_NTILE 3
+/* Stage-kernel tiles (cells per 256-thread workgroup): 0 = 16x4x4, 1 = 8x8x4, 2 = 64x2x2,
+ * 3 = 16x4x3 (192 cells: the faces of each direction fit one pass of the workgroup). */
+#define GRMHD_NTILE 4
 /* Stage-kernel scheduling in grmhd_rk_step: one workgroup per tile, or persistent
  * workgroups popping tiles from per-XCD atomic queues kept in the workspace. */
 enum { GRMHD_SCHED_GRID = 0, GRMHD_SCHED_QUEUE = 1 };
@@ -107,7 +108,8 @@ typedef struct {
   int32_t precision;  /* GRMHD_FP64 | GRMHD_MIXED */
   int32_t wenoz_p;    /* WENO-Z exponent: 1 or 2 */
   int32_t c2p_maxit;  /* iteration cap of each con2prim method, e.g. 100 */
-  int32_t tile;       /* stage-kernel tile shape: -1 = library choice, else 0 .. GRMHD_NTILE-1 */
+  int32_t tile;       /* stage-kernel tile shape: -1 = library choice (16x4x3 for FP64, 16x4x4 for
+                       * mixed precision), else 0 .. GRMHD_NTILE-1 */
   int32_t schedule;   /* GRMHD_SCHED_GRID | GRMHD_SCHED_QUEUE (grmhd_rk_step only) */
   double eos_gamma;   /* Gamma-law EOS p = (Gamma - 1) rho eps, Gamma > 1 */
   double weno_eps;    /* WENO5-JS epsilon, e.g. 1e-6 */
@@ -167,9 +169,12 @@ int grmhd_rhs(const grmhd_domain* dom, const grmhd_params* par, const grmhd_metr
  * con2prim(U^n), then per stage s: U_{s+1} = U^n + c_s ((U_s - U^n) + dt L(U_s))
  * with con2prim of each new stage state, ending with P consistent with
  * U^{n+1}.  U, P are updated in place.  stage_ckpt: NULL, or device memory
- * for nstage * 8 * cell_stride doubles receiving U^n and the stage states
- * (after their con2prim) for the adjoint.  max_rate / n_fail as above,
- * accumulated over all stages.  ws: grmhd_workspace_bytes() bytes. */
+ * for nstage * 8 * cell_stride doubles receiving the primitives of U^n and of
+ * the stage states (as con2prim recovered them) for the adjoint.  max_rate / n_fail as above,
+ * accumulated over all stages.  The con2prim of each stage state runs inside
+ * the stage kernel; the primitives alternate between P and a copy in the
+ * workspace and end in P.  ws: grmhd_workspace_bytes() bytes (two 8-field sets
+ * and 256 bytes of tile-queue counters). */
 int grmhd_rk_step(const grmhd_domain* dom, const grmhd_params* par, const grmhd_metric* met,
                   double* U, double* P, double dt, int32_t scheme, double* stage_ckpt,
                   double* max_rate, int64_t* n_fail, void* ws, size_t ws_bytes, void* stream);
@@ -181,15 +186,14 @@ int grmhd_con2prim_adjoint(const grmhd_domain* dom, const grmhd_params* par, con
                            const double* P, const double* gP, double* gU, void* stream);
 
 /* Adjoint of one grmhd_rk_step: gU_in = (dU^{n+1}/dU^n)^T gU_out on interior
- * cells, from the stage checkpoints that grmhd_rk_step wrote (U^n and the
- * stage states after their con2prim).  Per stage, in reverse: con2prim of the
- * checkpoint (P is the guess on input and scratch; it ends as the primitives
- * of U^n), then the transposed flux divergence, HLLE and reconstruction
- * (scattered with FP64 atomics, so the last bits can vary between runs), the
- * source-term VJP, con2prim through the implicit-function theorem and the
- * transposed stage combine.  Branches (minmod, max/min of the wave speeds,
- * positivity fallback) follow the forward choice; atmosphere resets are not
- * differentiated.  FP64 whatever par->precision says.
+ * cells, from the stage checkpoints that grmhd_rk_step wrote (the primitives
+ * of U^n and of the stage states).  Per stage, in reverse: the transposed flux
+ * divergence, HLLE and reconstruction (scattered with FP64 atomics, so the
+ * last bits can vary between runs), the source-term VJP, con2prim through the
+ * implicit-function theorem and the transposed stage combine.  Branches
+ * (minmod, max/min of the wave speeds, positivity fallback) follow the forward
+ * choice; atmosphere resets are not differentiated.  P receives the primitives
+ * of U^n.  FP64 whatever par->precision says.
  * ws: grmhd_workspace_bytes(..., for_adjoint = 1) bytes. */
 int grmhd_rk_step_adjoint(const grmhd_domain* dom, const grmhd_params* par, const grmhd_metric* met,
                           const double* stage_ckpt, double* P, double dt, int32_t scheme, const double* gU_out,

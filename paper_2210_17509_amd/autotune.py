@@ -17,7 +17,7 @@ import torch
 from . import grmhd as G
 
 _CACHE = {}
-NTILE = 3
+NTILE = G.GRMHD_NTILE
 
 
 def _key(dom, par):

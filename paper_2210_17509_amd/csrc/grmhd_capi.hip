@@ -36,9 +36,9 @@ constexpr int RECON_WENOZ2 = GRMHD_RECON_WENOZ + 1;
 constexpr size_t QUEUE_BYTES = 256;  // per-XCD tile-queue counters at the end of the step workspace
 
 // tile shapes of the stage kernel (TX * TY * TZ = 256)
-constexpr int TILE_X[NTILE] = {16, 8, 64};
-constexpr int TILE_Y[NTILE] = {4, 8, 2};
-constexpr int TILE_Z[NTILE] = {4, 4, 2};
+constexpr int TILE_X[NTILE] = {16, 8, 64, 16};
+constexpr int TILE_Y[NTILE] = {4, 8, 2, 4};
+constexpr int TILE_Z[NTILE] = {4, 4, 2, 3};
 
 struct StageArgs {
   Table tab;
@@ -57,14 +57,21 @@ struct StageArgs {
   double* max_rate;
   unsigned int* queue;  // non-null: persistent launch over per-XCD tile queues
   int32_t persist_blocks;
+  // mode 1 only, nullable: con2prim of each new cell state inside the stage
+  // kernel, guessed from P; results to Pout (which must not alias P: other
+  // tiles still read P) and to the checkpoint ckpt
+  double* Pout;
+  double* ckpt;
+  unsigned long long* n_fail;
 };
 
 struct CellArgs {
   Table tab;
   double* U;
-  double* P;
+  double* P;     // guess
+  double* Pout;  // result (may be P)
   int32_t write_u;  // 0: U is read only (atmosphere resets are not written back)
-  double* ckpt;  // nullable copy of U after con2prim
+  double* ckpt;  // nullable copy of the recovered primitives
   int32_t* status;
   unsigned long long* n_fail;
   const double* __restrict__ gamma;
@@ -194,16 +201,17 @@ __device__ __forceinline__ void direction_phase(const StageArgs& a, const KBox& 
   constexpr int BX = (D == 2) ? 1 : 2;             // second other axis
   const int tid = threadIdx.x;
   const int lastD = min(T_D, bx.n[D] - org[D]);    // face index after the tile's last valid cell
-  for (int job = tid; job < 256 + NEXTRA; job += 256) {
+  constexpr int NCELL = TX * TY * TZ;
+  for (int job = tid; job < NCELL + NEXTRA; job += 256) {
     int fl[3];
     bool ok;
-    if (job < 256) {
+    if (job < NCELL) {
       fl[0] = l[0];
       fl[1] = l[1];
       fl[2] = l[2];
       ok = valid;
     } else {
-      const int e = job - 256;
+      const int e = job - NCELL;
       fl[AX] = e % TA;
       fl[BX] = e / TA;
       fl[D] = lastD;
@@ -234,7 +242,7 @@ __device__ __forceinline__ void direction_phase(const StageArgs& a, const KBox& 
 template <int RECON, typename R, bool SHIFT, int TI>
 __device__ __forceinline__ void stage_tile(const StageArgs& a, int tg,
                                            double (*sF)[TileGeo<TILE_X[TI], TILE_Y[TI], TILE_Z[TI]>::maxslots()],
-                                           double* sV, double& rate) {
+                                           double* sV, double& rate, unsigned long long& fail) {
   constexpr int TX = TILE_X[TI], TY = TILE_Y[TI], TZ = TILE_Z[TI];
   using G = TileGeo<TX, TY, TZ>;
   const int b = find_box(a.tab.tile_prefix + TI * (a.tab.nbox + 1), a.tab.nbox, tg);
@@ -245,7 +253,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int tg,
   const int tid = threadIdx.x;
   const int l[3] = {tid % TX, (tid / TX) % TY, tid / (TX * TY)};
   const int i = org[0] + l[0], j = org[1] + l[1], k = org[2] + l[2];
-  const bool valid = (i < bx.n[0]) && (j < bx.n[1]) && (k < bx.n[2]);
+  const bool valid = (tid < TX * TY * TZ) && (i < bx.n[0]) && (j < bx.n[1]) && (k < bx.n[2]);
   const double* __restrict__ Pb = a.P + bx.cell_off;
   // Stage the tile's vertex metric in LDS: every face and cell of the tile reads
   // its vertices from this block.  Vertices past the box's last interior vertex
@@ -287,32 +295,56 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int tg,
 #pragma unroll
       for (int q = 0; q < 8; ++q) stg(a.Uout + q * a.cs + bx.cell_off, (uint32_t)c, acc[q] + S[q]);
     } else {
+      double u[8];
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
         const double un = ldg(a.Un + q * a.cs + bx.cell_off, (uint32_t)c);
         const double us = ldg(a.Us + q * a.cs + bx.cell_off, (uint32_t)c);
-        stg(a.Uout + q * a.cs + bx.cell_off, (uint32_t)c, un + a.cstage * ((us - un) + a.dt * (acc[q] + S[q])));
+        u[q] = un + a.cstage * ((us - un) + a.dt * (acc[q] + S[q]));
       }
+      if (a.Pout) {
+        // con2prim of the new state while it is in registers (the same routine,
+        // inputs and metric as the con2prim kernel); an atmosphere reset
+        // rewrites u as well
+        const int st = c2p_cell(cm.g, cm.gi, cm.sqrtg, a.ph, u, P);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) stg(a.Pout + q * a.cs + bx.cell_off, (uint32_t)c, P[q]);
+        if (a.ckpt) {
+#pragma unroll
+          for (int q = 0; q < 8; ++q) stg(a.ckpt + q * a.cs + bx.cell_off, (uint32_t)c, P[q]);
+        }
+        fail += (st >= C2P_NOCONV && st <= C2P_NONFINITE) ? 1ull : 0ull;
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) stg(a.Uout + q * a.cs + bx.cell_off, (uint32_t)c, u[q]);
     }
   }
 }
 
-// Waves per SIMD each stage-kernel instance is compiled for: FP32 faces fit three
-// (168 VGPRs with a small spill), FP64 faces two.
-template <typename R> struct StageWaves {
-  static constexpr int value = (sizeof(R) == 4) ? 3 : 2;
+// Sum of the per-thread failure counts of a wave, added by its first lane.
+__device__ __forceinline__ void wave_count_atomic(unsigned long long v, unsigned long long* target) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  if ((threadIdx.x & 63) == 0 && v) atomicAdd(target, v);
+}
+
+// Waves per SIMD each stage-kernel instance is compiled for: FP32 faces without
+// shift fit three (168 VGPRs with a small spill), the others two.
+template <typename R, bool SHIFT> struct StageWaves {
+  static constexpr int value = (sizeof(R) == 4 && !SHIFT) ? 3 : 2;
 };
 
 // One workgroup per tile.  Workgroups are dispatched round-robin over the 8
 // XCDs; each XCD gets a contiguous run of tiles so tiles sharing halos share an L2.
 template <int RECON, typename R, bool SHIFT, int TI>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(StageWaves<R>::value))) void k_stage(StageArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(StageWaves<R, SHIFT>::value))) void k_stage(StageArgs a) {
   using G = TileGeo<TILE_X[TI], TILE_Y[TI], TILE_Z[TI]>;
   __shared__ double sF[8][G::maxslots()];
   __shared__ double sV[G::nvf(SHIFT) * G::NVB];
   double rate = 0.0;
-  stage_tile<RECON, R, SHIFT, TI>(a, xcd_tile(blockIdx.x, gridDim.x), sF, sV, rate);
+  unsigned long long fail = 0;
+  stage_tile<RECON, R, SHIFT, TI>(a, xcd_tile(blockIdx.x, gridDim.x), sF, sV, rate, fail);
   if (a.max_rate) block_max_atomic(rate, a.max_rate);
+  if (a.n_fail) wave_count_atomic(fail, a.n_fail);
 }
 
 // Persistent workgroups: each pops tiles from the queue of its XCD (a
@@ -320,7 +352,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(StageWaves<
 // counters live in the workspace and are zeroed by k_reset_queue before the
 // launch; every workgroup leaves the loop once its counter passes the range.
 template <int RECON, typename R, bool SHIFT, int TI>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(StageWaves<R>::value))) void k_stage_queue(StageArgs a, unsigned int* queue,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(StageWaves<R, SHIFT>::value))) void k_stage_queue(StageArgs a, unsigned int* queue,
                                                                                                     int ntile) {
   using G = TileGeo<TILE_X[TI], TILE_Y[TI], TILE_Z[TI]>;
   __shared__ double sF[8][G::maxslots()];
@@ -331,15 +363,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(StageWaves<
   const int lo = x * q + (x < r ? x : r);
   const int cnt = q + (x < r ? 1 : 0);
   double rate = 0.0;
+  unsigned long long fail = 0;
   for (;;) {
     if (threadIdx.x == 0) s_tile = (int)atomicAdd(queue + x, 1u);
     __syncthreads();
     const int k = s_tile;
     __syncthreads();
     if (k >= cnt) break;
-    stage_tile<RECON, R, SHIFT, TI>(a, lo + k, sF, sV, rate);
+    stage_tile<RECON, R, SHIFT, TI>(a, lo + k, sF, sV, rate, fail);
   }
   if (a.max_rate) block_max_atomic(rate, a.max_rate);
+  if (a.n_fail) wave_count_atomic(fail, a.n_fail);
 }
 
 __global__ void k_reset_queue(unsigned int* queue) {
@@ -380,14 +414,14 @@ __global__ __launch_bounds__(C2P_BLOCK) void k_con2prim(CellArgs a) {
     }
     const int st = c2p_cell(cm.g, cm.gi, cm.sqrtg, a.ph, U, P);
 #pragma unroll
-    for (int q = 0; q < 8; ++q) a.P[q * a.cs + cc] = P[q];
+    for (int q = 0; q < 8; ++q) a.Pout[q * a.cs + cc] = P[q];
     if (a.write_u && st != C2P_OK && st != C2P_FALLBACK) {
 #pragma unroll
       for (int q = 0; q < 8; ++q) a.U[q * a.cs + cc] = U[q];
     }
     if (a.ckpt) {
 #pragma unroll
-      for (int q = 0; q < 8; ++q) a.ckpt[q * a.cs + cc] = U[q];
+      for (int q = 0; q < 8; ++q) a.ckpt[q * a.cs + cc] = P[q];
     }
     if (a.status) a.status[cc] = st;
     fail = (st >= C2P_NOCONV && st <= C2P_NONFINITE) ? 1ull : 0ull;
@@ -996,7 +1030,9 @@ int persistent_blocks() {
 int pick_tile(const grmhd_domain* dom, const grmhd_params* par) {
   if (par->tile >= 0) return par->tile;
   (void)dom;
-  return 0;
+  // FP64 faces: 16x4x3 (every direction's faces in one pass of the workgroup);
+  // FP32 faces (three waves per SIMD): 16x4x4
+  return par->precision == GRMHD_MIXED ? 0 : 3;
 }
 
 template <int RECON, typename R, bool SHIFT, int TI>
@@ -1017,7 +1053,8 @@ hipError_t launch_stage_r(const StageArgs& a, int64_t blocks, hipStream_t s) {
   switch (a.tile) {
     case 0: return launch_stage_t<RECON, R, SHIFT, 0>(a, blocks, s);
     case 1: return launch_stage_t<RECON, R, SHIFT, 1>(a, blocks, s);
-    default: return launch_stage_t<RECON, R, SHIFT, 2>(a, blocks, s);
+    case 2: return launch_stage_t<RECON, R, SHIFT, 2>(a, blocks, s);
+    default: return launch_stage_t<RECON, R, SHIFT, 3>(a, blocks, s);
   }
 }
 
@@ -1047,11 +1084,13 @@ int check_metric(const grmhd_metric* m, bool need_alpha) {
 }
 
 hipError_t launch_c2p(const grmhd_domain* dom, const Prepared& pr, const KPhys& ph, const grmhd_metric* met, double* U,
-                      double* P, double* ckpt, int32_t* status, int64_t* n_fail, hipStream_t s) {
+                      double* P, double* ckpt, int32_t* status, int64_t* n_fail, hipStream_t s,
+                      double* Pout = nullptr) {
   CellArgs a;
   a.tab = make_table(dom);
   a.U = U;
   a.P = P;
+  a.Pout = Pout ? Pout : P;
   a.write_u = 1;
   a.ckpt = ckpt;
   a.status = status;
@@ -1085,6 +1124,9 @@ StageArgs stage_args(const grmhd_domain* dom, const grmhd_params* par, const KPh
   a.max_rate = nullptr;
   a.queue = nullptr;
   a.persist_blocks = 0;
+  a.Pout = nullptr;
+  a.ckpt = nullptr;
+  a.n_fail = nullptr;
   return a;
 }
 
@@ -1136,7 +1178,7 @@ int grmhd_domain_prepare(const grmhd_domain* dom, void* stream) {
   int32_t* tp = c2p + (nb + 1);
   int32_t* fp = tp + NTILE * (nb + 1);
   Prepared pr;
-  int64_t acc_c2p = 0, acc_t[NTILE] = {0, 0, 0}, acc_f[3] = {0, 0, 0};
+  int64_t acc_c2p = 0, acc_t[NTILE] = {}, acc_f[3] = {0, 0, 0};
   for (int b = 0; b < nb; ++b) {
     const grmhd_box& x = dom->box[b];
     KBox& k = kb[b];
@@ -1250,7 +1292,7 @@ size_t grmhd_workspace_bytes(const grmhd_domain* dom, const grmhd_params* par, i
   (void)scheme;
   if (!dom || dom->cell_stride < 1) return 0;
   const size_t field = sizeof(double) * 8 * (size_t)dom->cell_stride;
-  return for_adjoint ? 2 * field : field + QUEUE_BYTES;
+  return for_adjoint ? 2 * field : 2 * field + QUEUE_BYTES;
 }
 
 int grmhd_rk_step(const grmhd_domain* dom, const grmhd_params* par, const grmhd_metric* met, double* U, double* P,
@@ -1273,28 +1315,37 @@ int grmhd_rk_step(const grmhd_domain* dom, const grmhd_params* par, const grmhd_
   static const double c2[2] = {1.0, 0.5};
   const double* cst = scheme == GRMHD_SSPRK2 ? c2 : c3;
   const int nst = scheme == GRMHD_SSPRK2 ? 2 : 3;
-  double* W1 = static_cast<double*>(ws);
+  // Workspace: the intermediate stage state W1, a second primitive buffer Pw and
+  // the tile-queue counters.  Each stage kernel recovers the primitives of the
+  // state it writes (con2prim fused into the stage), so the primitives alternate
+  // between P and Pw; the first recovery (of U^n) starts on the buffer that
+  // makes the last stage end in P.
   const size_t fsz = 8 * (size_t)dom->cell_stride;
-  hipError_t e = launch_c2p(dom, pr, ph, met, U, P, stage_ckpt, nullptr, n_fail, s);
+  double* W1 = static_cast<double*>(ws);
+  double* Pw = W1 + fsz;
+  double* Pcur = (nst % 2) ? Pw : P;
+  hipError_t e = launch_c2p(dom, pr, ph, met, U, P, stage_ckpt, nullptr, n_fail, s, Pcur);
   if (e != hipSuccess) return fail_hip(e, "k_con2prim");
-  StageArgs a = stage_args(dom, par, ph, met, P);
+  StageArgs a = stage_args(dom, par, ph, met, Pcur);
   a.mode = 1;
   a.dt = dt;
   a.max_rate = max_rate;
+  a.n_fail = reinterpret_cast<unsigned long long*>(n_fail);
   a.Un = U;
   if (par->schedule == GRMHD_SCHED_QUEUE) {
-    a.queue = reinterpret_cast<unsigned int*>(static_cast<char*>(ws) + sizeof(double) * fsz);
+    a.queue = reinterpret_cast<unsigned int*>(static_cast<char*>(ws) + sizeof(double) * 2 * fsz);
     a.persist_blocks = persistent_blocks();
   }
   for (int st = 0; st < nst; ++st) {
     a.Us = (st == 0) ? U : W1;
     a.Uout = (st == nst - 1) ? U : W1;
     a.cstage = cst[st];
+    a.P = Pcur;
+    a.Pout = (Pcur == P) ? Pw : P;
+    a.ckpt = (stage_ckpt && st + 1 < nst) ? stage_ckpt + (st + 1) * fsz : nullptr;
     e = launch_stage(a, par->recon, par->precision, pr.tiles[a.tile], s);
     if (e != hipSuccess) return fail_hip(e, "k_stage");
-    double* ck = (stage_ckpt && st + 1 < nst) ? stage_ckpt + (st + 1) * fsz : nullptr;
-    e = launch_c2p(dom, pr, ph, met, a.Uout, P, ck, nullptr, n_fail, s);
-    if (e != hipSuccess) return fail_hip(e, "k_con2prim");
+    Pcur = a.Pout;
   }
   return GRMHD_OK;
 }
@@ -1358,24 +1409,12 @@ int grmhd_rk_step_adjoint(const grmhd_domain* dom, const grmhd_params* par, cons
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail_hip(e, "adjoint setup");
   for (int st = nst - 1; st >= 0; --st) {
-    // primitives of the stage state (checkpoints are not modified)
-    CellArgs ca;
-    ca.tab = tab;
-    ca.U = const_cast<double*>(stage_ckpt + st * fsz);
-    ca.P = P;
-    ca.write_u = 0;
-    ca.ckpt = nullptr;
-    ca.status = nullptr;
-    ca.n_fail = nullptr;
-    ca.gamma = met->gamma;
-    ca.cs = dom->cell_stride;
-    ca.vs = dom->vert_stride;
-    ca.ph = ph;
-    hipLaunchKernelGGL(k_con2prim, dim3(cb), dim3(C2P_BLOCK), 0, s, ca);
+    // the primitives of the stage state, as the forward step recovered them
+    const double* Ps = stage_ckpt + st * fsz;
     hipLaunchKernelGGL(k_fill, dim3(cb), dim3(C2P_BLOCK), 0, s, tab, Pbar, dom->cell_stride, 0.0);
     AdjArgs fa;
     fa.tab = tab;
-    fa.P = P;
+    fa.P = Ps;
     fa.V = V;
     fa.Pbar = Pbar;
     fa.alpha = met->alpha;
@@ -1388,7 +1427,7 @@ int grmhd_rk_step_adjoint(const grmhd_domain* dom, const grmhd_params* par, cons
     if (e != hipSuccess) return fail_hip(e, "k_adj_face");
     AdjCellArgs a;
     a.tab = tab;
-    a.P = P;
+    a.P = Ps;
     a.V = V;
     a.Gn = gU_in;
     a.Pbar = Pbar;
@@ -1405,7 +1444,9 @@ int grmhd_rk_step_adjoint(const grmhd_domain* dom, const grmhd_params* par, cons
     e = launch_adj_cell(a, pr, s);
     if (e != hipSuccess) return fail_hip(e, "k_adj_cell");
   }
-  return GRMHD_OK;
+  hipLaunchKernelGGL(k_copy, dim3(cb), dim3(C2P_BLOCK), 0, s, tab, stage_ckpt, P, dom->cell_stride);
+  e = hipGetLastError();
+  return e == hipSuccess ? GRMHD_OK : fail_hip(e, "adjoint P");
 }
 
 int grmhd_timing_enable(int32_t on) {

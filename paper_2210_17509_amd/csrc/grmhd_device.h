@@ -9,11 +9,13 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "grmhd.h"
+
 namespace gk {
 
 // ---------------------------------------------------------------- launch tables
 
-constexpr int NTILE = 3;  // compiled stage-kernel tile shapes
+constexpr int NTILE = GRMHD_NTILE;  // compiled stage-kernel tile shapes
 constexpr int C2P_BLOCK = 256;
 
 // Per-box data the kernels read (derived on the host from grmhd_box).

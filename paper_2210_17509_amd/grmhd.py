@@ -150,6 +150,7 @@ class Metric:
 
 
 GRMHD_SCHED_GRID, GRMHD_SCHED_QUEUE = 0, 1
+GRMHD_NTILE = 4  # stage-kernel tile shapes: 16x4x4, 8x8x4, 64x2x2, 16x4x3
 
 
 def make_params(p, tile=-1, schedule=GRMHD_SCHED_GRID):

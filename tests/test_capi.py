@@ -106,5 +106,5 @@ def test_workspace_size(lib):
     from paper_2210_17509_amd import grmhd as G
     d, keep = _domain(G)
     par = G.grmhd_params(1, 0, 1, 100, -1, 0, 5 / 3, 1e-6, 1e-40, 1e-12, 1e-10, 100.0, 2.0)
-    assert G._lib.grmhd_workspace_bytes(ctypes.byref(d), ctypes.byref(par), 0, 0) == 8 * 8 * d.cell_stride + 256
+    assert G._lib.grmhd_workspace_bytes(ctypes.byref(d), ctypes.byref(par), 0, 0) == 2 * 8 * 8 * d.cell_stride + 256
     assert G._lib.grmhd_workspace_bytes(ctypes.byref(d), ctypes.byref(par), 0, 1) == 2 * 8 * 8 * d.cell_stride
