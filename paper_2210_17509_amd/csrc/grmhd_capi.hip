@@ -613,42 +613,67 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     give[o] = (D == 0) && live && m >= 0 && m < nD && owner >= 0 && owner < 64;
     take[o] = (D == 0) && live && c < nD && from >= 0 && from < 64 && fc >= 0 && fc <= nD;
   }
-  // reverse of the reconstruction, scattered onto the stencil cells (one field at
-  // a time: only one stencil is live)
+  // reverse of the reconstruction, scattered onto the stencil cells, one field at
+  // a time (only one stencil is live).  x faces prefetch the next field's
+  // stencil during the current field's work (timed faster there; for y and z
+  // faces the extra live registers cost more than the hidden latency).  The
+  // per-field adjoints are shifted down one slot per iteration so every
+  // register index is static.
+  constexpr int O0 = (RECON == GRMHD_RECON_MINMOD) ? 1 : 0, O1 = (RECON == GRMHD_RECON_MINMOD) ? 5 : 6;
+  double snx[6] = {0, 0, 0, 0, 0, 0};
+  if constexpr (D == 0) {
+#pragma unroll
+    for (int o = O0; o < O1; ++o) snx[o] = Pb[idx[o]];
+  }
 #pragma clang loop unroll(disable)
   for (int q = 0; q < 8; ++q) {
-    const double* __restrict__ f = Pb + q * a.cs;
-    double sb[6] = {0, 0, 0, 0, 0, 0};
-    if (RECON == GRMHD_RECON_MINMOD) {
-      const double s1 = f[idx[1]], s2 = f[idx[2]], s3 = f[idx[3]], s4 = f[idx[4]];
-      double g3[3];
-      if (fbL) sb[2] += qbL[q];
-      else {
-        minmod_grad(s1, s2, s3, g3);
-        sb[1] += qbL[q] * g3[0]; sb[2] += qbL[q] * g3[1]; sb[3] += qbL[q] * g3[2];
-      }
-      if (fbR) sb[3] += qbR[q];
-      else {
-        minmod_grad(s4, s3, s2, g3);
-        sb[4] += qbR[q] * g3[0]; sb[3] += qbR[q] * g3[1]; sb[2] += qbR[q] * g3[2];
+    double s[6] = {0, 0, 0, 0, 0, 0};
+    if constexpr (D == 0) {
+#pragma unroll
+      for (int o = 0; o < 6; ++o) s[o] = snx[o];
+      if (q < 7) {
+        const double* __restrict__ fn = Pb + (q + 1) * a.cs;
+#pragma unroll
+        for (int o = O0; o < O1; ++o) snx[o] = fn[idx[o]];
       }
     } else {
-      double s[6];
+      const double* __restrict__ f = Pb + q * a.cs;
 #pragma unroll
-      for (int o = 0; o < 6; ++o) s[o] = f[idx[o]];
+      for (int o = O0; o < O1; ++o) s[o] = f[idx[o]];
+    }
+    const double aL = qbL[0], aR = qbR[0];
+#pragma unroll
+    for (int t = 0; t < 7; ++t) {
+      qbL[t] = qbL[t + 1];
+      qbR[t] = qbR[t + 1];
+    }
+    double sb[6] = {0, 0, 0, 0, 0, 0};
+    if (RECON == GRMHD_RECON_MINMOD) {
+      double g3[3];
+      if (fbL) sb[2] += aL;
+      else {
+        minmod_grad(s[1], s[2], s[3], g3);
+        sb[1] += aL * g3[0]; sb[2] += aL * g3[1]; sb[3] += aL * g3[2];
+      }
+      if (fbR) sb[3] += aR;
+      else {
+        minmod_grad(s[4], s[3], s[2], g3);
+        sb[4] += aR * g3[0]; sb[3] += aR * g3[1]; sb[2] += aR * g3[2];
+      }
+    } else {
       double g5[5];
-      if (fbL) sb[2] += qbL[q];
+      if (fbL) sb[2] += aL;
       else {
         weno5_grad<ZW, ZP>(s, eps, ZP, g5);
 #pragma unroll
-        for (int o = 0; o < 5; ++o) sb[o] += qbL[q] * g5[o];
+        for (int o = 0; o < 5; ++o) sb[o] += aL * g5[o];
       }
-      if (fbR) sb[3] += qbR[q];
+      if (fbR) sb[3] += aR;
       else {
         const double sr[5] = {s[5], s[4], s[3], s[2], s[1]};
         weno5_grad<ZW, ZP>(sr, eps, ZP, g5);
 #pragma unroll
-        for (int o = 0; o < 5; ++o) sb[5 - o] += qbR[q] * g5[o];
+        for (int o = 0; o < 5; ++o) sb[5 - o] += aR * g5[o];
       }
     }
     if (D == 0) {
@@ -726,9 +751,10 @@ __device__ __forceinline__ void solve_dUdP_T(const double (*J)[8], double sqrtg,
 struct AdjCellArgs {
   Table tab;
   const double* __restrict__ P;
-  double* V;                      // in: v = adjoint of U_{s+1}; out (stage > 0): adjoint of U_s
+  const double* Vin;              // v = adjoint of U_{s+1}
+  double* V;                      // out (stage > 0): adjoint of U_s (may alias Vin)
   double* Gn;                     // accumulated adjoint of U^n
-  const double* __restrict__ Pbar;
+  double* Pbar;                   // read, then cleared for the next stage's faces
   const double* __restrict__ alpha;
   const double* __restrict__ beta;
   const double* __restrict__ gamma;
@@ -748,22 +774,26 @@ __global__ __launch_bounds__(C2P_BLOCK) __attribute__((amdgpu_waves_per_eu(2))) 
   if (!cell_of(a.tab, blockIdx.x, threadIdx.x, b, c, vb)) return;
   const KBox& bx = a.tab.box[b];
   const int64_t cc = bx.cell_off + c;
+  // the cell's 8 vertices, loaded once for the centre metric and its derivatives
+  CornerVerts<SHIFT ? 10 : 7> cv;
+  cv.load(GlobalVerts{a.alpha + bx.vert_off, SHIFT ? a.beta + bx.vert_off : nullptr, a.gamma + bx.vert_off, a.vs},
+          vb, bx.VX, bx.VXY);
   CentreMetric cm;
-  const GlobalVerts gv{a.alpha + bx.vert_off, SHIFT ? a.beta + bx.vert_off : nullptr, a.gamma + bx.vert_off, a.vs};
-  centre_metric<SHIFT, true>(gv, vb, bx.VX, bx.VXY, cm);
+  centre_metric<SHIFT, true>(cv, 0u, 2u, 4u, cm);
   double P[8], v[8], pb[8];
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
     P[q] = a.P[q * a.cs + cc];
-    v[q] = a.V[q * a.cs + cc];
+    v[q] = a.Vin[q * a.cs + cc];
     pb[q] = (a.mode == 0) ? a.Pbar[q * a.cs + cc] : v[q];
+    if (a.mode == 0) a.Pbar[q * a.cs + cc] = 0.0;
   }
   // (dS/dP)^T v by reverse mode, then dU/dP by forward-mode dual numbers, one
   // tangent (primitive) per pass; the passes are real loop iterations so only
   // one pass's dual numbers are live at a time (two waves per SIMD fit).
   if (a.mode == 0) {
     MetricDeriv md;
-    metric_deriv<SHIFT>(gv, vb, bx.VX, bx.VXY, bx.inv_dx, md);
+    metric_deriv<SHIFT>(cv, 0u, 2u, 4u, bx.inv_dx, md);
     sources_vjp<SHIFT>(cm, md, P, a.ph.gam, v, pb);
   }
   constexpr int NU = 1;
@@ -1361,7 +1391,8 @@ int grmhd_con2prim_adjoint(const grmhd_domain* dom, const grmhd_params* par, con
   AdjCellArgs a;
   a.tab = make_table(dom);
   a.P = P;
-  a.V = const_cast<double*>(gP);
+  a.Vin = gP;
+  a.V = nullptr;  // not written in this mode
   a.Gn = gU;
   a.Pbar = nullptr;
   a.alpha = met->gamma;  // not read in this mode (only the spatial metric enters dU/dP)
@@ -1404,18 +1435,20 @@ int grmhd_rk_step_adjoint(const grmhd_domain* dom, const grmhd_params* par, cons
   double* Pbar = V + fsz;
   const Table tab = make_table(dom);
   const unsigned cb = (unsigned)pr.c2p_blocks;
-  hipLaunchKernelGGL(k_copy, dim3(cb), dim3(C2P_BLOCK), 0, s, tab, gU_out, V, dom->cell_stride);
+  // P-bar starts at zero; each stage's cell kernel clears it again after use
+  hipLaunchKernelGGL(k_fill, dim3(cb), dim3(C2P_BLOCK), 0, s, tab, Pbar, dom->cell_stride, 0.0);
   hipLaunchKernelGGL(k_fill, dim3(cb), dim3(C2P_BLOCK), 0, s, tab, gU_in, dom->cell_stride, 0.0);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail_hip(e, "adjoint setup");
   for (int st = nst - 1; st >= 0; --st) {
     // the primitives of the stage state, as the forward step recovered them
     const double* Ps = stage_ckpt + st * fsz;
-    hipLaunchKernelGGL(k_fill, dim3(cb), dim3(C2P_BLOCK), 0, s, tab, Pbar, dom->cell_stride, 0.0);
+    // the adjoint of U_{s+1}: gU_out for the last stage, then the workspace copy
+    const double* Vin = (st == nst - 1) ? gU_out : V;
     AdjArgs fa;
     fa.tab = tab;
     fa.P = Ps;
-    fa.V = V;
+    fa.V = Vin;
     fa.Pbar = Pbar;
     fa.alpha = met->alpha;
     fa.beta = met->beta;
@@ -1428,6 +1461,7 @@ int grmhd_rk_step_adjoint(const grmhd_domain* dom, const grmhd_params* par, cons
     AdjCellArgs a;
     a.tab = tab;
     a.P = Ps;
+    a.Vin = Vin;
     a.V = V;
     a.Gn = gU_in;
     a.Pbar = Pbar;

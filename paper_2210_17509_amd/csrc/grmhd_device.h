@@ -152,6 +152,21 @@ template <int STRIDE> struct LdsVerts {
   __device__ __forceinline__ double operator()(int f, uint32_t v) const { return s[f * STRIDE + v]; }
 };
 
+// The 8 vertices of one cell held in registers: field f of corner
+// dx + 2 dy + 4 dz at index dx + 2 dy + 4 dz (corner strides 1, 2, 4).
+template <int NF> struct CornerVerts {
+  double v[NF][8];
+  template <typename V>
+  __device__ __forceinline__ void load(const V& vt, uint32_t vb, uint32_t VX, uint32_t VXY) {
+    const uint32_t o[8] = {0u, 1u, VX, VX + 1u, VXY, VXY + 1u, VXY + VX, VXY + VX + 1u};
+#pragma unroll
+    for (int f = 0; f < NF; ++f)
+#pragma unroll
+      for (int c = 0; c < 8; ++c) v[f][c] = vt(f, vb + o[c]);
+  }
+  __device__ __forceinline__ double operator()(int f, uint32_t c) const { return v[f][c]; }
+};
+
 // ---------------------------------------------------------------- face metric
 
 template <typename R> struct FaceMetric {
