@@ -112,6 +112,57 @@ template <int N> __device__ __forceinline__ DN<N> sqrt_r(const DN<N>& a) {
   return r;
 }
 
+// ---------------------------------------------------------------- dU/dP
+
+// Rows D, S_j, tau of dU/dP for Eqs. (p2c1)-(p2c4), written out: J[r][c] =
+// dU_r/dP_c, P = (rho, v^1..3, eps, B^1..3).  For the Gamma law rho h = rho (1 +
+// Gamma eps), and with H = rho h W^2 + B^2 the conserved variables reduce to
+//   D = sqrt(g) rho W,  S_j = sqrt(g) (H v_j - (B.v) B_j),
+//   tau = sqrt(g) (H - p - B^2 / (2 W^2) - (B.v)^2 / 2) - D,
+// with dW/dv^k = W^3 v_k (the ℬ rows are sqrt(g) times the identity).
+__device__ __forceinline__ void p2c_jacobian(const double* g, double sqrtg, double gm1, const double* P,
+                                             double J[5][8]) {
+  const double rho = P[0], eps = P[4], gam = gm1 + 1.0;
+  double vl[3], Bl[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    vl[i] = g[sidx(i, 0)] * P[1] + g[sidx(i, 1)] * P[2] + g[sidx(i, 2)] * P[3];
+    Bl[i] = g[sidx(i, 0)] * P[5] + g[sidx(i, 1)] * P[6] + g[sidx(i, 2)] * P[7];
+  }
+  const double v2 = vl[0] * P[1] + vl[1] * P[2] + vl[2] * P[3];
+  const double W = 1.0 / sqrt_r(1.0 - v2), W2 = W * W, W3 = W2 * W, W4 = W2 * W2;
+  const double B2 = Bl[0] * P[5] + Bl[1] * P[6] + Bl[2] * P[7];
+  const double Bv = Bl[0] * P[1] + Bl[1] * P[2] + Bl[2] * P[3];
+  const double dhr = 1.0 + gam * eps;  // d(rho h)/d rho
+  const double rh = rho * dhr;
+  const double H = rh * W2 + B2;
+  const double s = sqrtg;
+  J[0][0] = s * W;
+  J[0][4] = 0.0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    J[0][1 + k] = s * rho * W3 * vl[k];
+    J[0][5 + k] = 0.0;
+  }
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    J[1 + j][0] = s * dhr * W2 * vl[j];
+    J[1 + j][4] = s * gam * rho * W2 * vl[j];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      J[1 + j][1 + k] = s * (2.0 * rh * W4 * vl[k] * vl[j] + H * g[sidx(j, k)] - Bl[k] * Bl[j]);
+      J[1 + j][5 + k] = s * (2.0 * Bl[k] * vl[j] - vl[k] * Bl[j] - Bv * g[sidx(j, k)]);
+    }
+  }
+  J[4][0] = s * (dhr * W2 - gm1 * eps - W);
+  J[4][4] = s * (gam * rho * W2 - gm1 * rho);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    J[4][1 + k] = s * (2.0 * rh * W4 * vl[k] + B2 * vl[k] - Bv * Bl[k] - rho * W3 * vl[k]);
+    J[4][5 + k] = s * (2.0 * Bl[k] - Bl[k] / W2 - Bv * vl[k]);
+  }
+}
+
 // ---------------------------------------------------------------- sources
 
 // Reverse of tmunu_T: Pb += d/dP (Tb00 T00 + sum_i Tb0_i T^{0i} + sum_{i<=j} Tbij_ij T^{ij})

@@ -139,12 +139,11 @@ __device__ __forceinline__ void face_flux(const StageArgs& a, const KBox& bx, co
       constexpr bool z = (RECON >= GRMHD_RECON_WENOZ);
       constexpr int zp = (RECON == RECON_WENOZ2) ? 2 : 1;
       const R eps = (R)(z ? a.ph.wenoz_eps : a.ph.weno_eps);
-      if (z) {
-        PL[q] = weno5<true, zp>(s[0], s[1], s[2], s[3], s[4], eps, zp);
-        PR[q] = weno5<true, zp>(s[5], s[4], s[3], s[2], s[1], eps, zp);
+      if constexpr (sizeof(R) == 8) {
+        weno5_lr<z, zp>(s, eps, zp, PL[q], PR[q]);
       } else {
-        PL[q] = weno5<false>(s[0], s[1], s[2], s[3], s[4], eps, 1);
-        PR[q] = weno5<false>(s[5], s[4], s[3], s[2], s[1], eps, 1);
+        PL[q] = weno5<z, zp>(s[0], s[1], s[2], s[3], s[4], eps, zp);
+        PR[q] = weno5<z, zp>(s[5], s[4], s[3], s[2], s[1], eps, zp);
       }
     }
   }
@@ -327,16 +326,18 @@ __device__ __forceinline__ void wave_count_atomic(unsigned long long v, unsigned
   if ((threadIdx.x & 63) == 0 && v) atomicAdd(target, v);
 }
 
-// Waves per SIMD each stage-kernel instance is compiled for: FP32 faces without
-// shift fit three (168 VGPRs with a small spill), the others two.
-template <typename R, bool SHIFT> struct StageWaves {
-  static constexpr int value = (sizeof(R) == 4 && !SHIFT) ? 3 : 2;
+// Waves per SIMD each stage-kernel instance is compiled for: without shift three
+// (168 VGPRs with a spill of under 80 bytes; FP64 faces use the two-sided WENO,
+// which made that possible), except WENO-Z with p = 2 in FP64 (which would spill
+// ~300 bytes); with shift two.
+template <typename R, bool SHIFT, int RECON> struct StageWaves {
+  static constexpr int value = (!SHIFT && (sizeof(R) == 4 || RECON != RECON_WENOZ2)) ? 3 : 2;
 };
 
 // One workgroup per tile.  Workgroups are dispatched round-robin over the 8
 // XCDs; each XCD gets a contiguous run of tiles so tiles sharing halos share an L2.
 template <int RECON, typename R, bool SHIFT, int TI>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(StageWaves<R, SHIFT>::value))) void k_stage(StageArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(StageWaves<R, SHIFT, RECON>::value))) void k_stage(StageArgs a) {
   using G = TileGeo<TILE_X[TI], TILE_Y[TI], TILE_Z[TI]>;
   __shared__ double sF[8][G::maxslots()];
   __shared__ double sV[G::nvf(SHIFT) * G::NVB];
@@ -352,7 +353,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(StageWaves<
 // counters live in the workspace and are zeroed by k_reset_queue before the
 // launch; every workgroup leaves the loop once its counter passes the range.
 template <int RECON, typename R, bool SHIFT, int TI>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(StageWaves<R, SHIFT>::value))) void k_stage_queue(StageArgs a, unsigned int* queue,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(StageWaves<R, SHIFT, RECON>::value))) void k_stage_queue(StageArgs a, unsigned int* queue,
                                                                                                     int ntile) {
   using G = TileGeo<TILE_X[TI], TILE_Y[TI], TILE_Z[TI]>;
   __shared__ double sF[8][G::maxslots()];
@@ -788,33 +789,15 @@ __global__ __launch_bounds__(C2P_BLOCK) __attribute__((amdgpu_waves_per_eu(2))) 
     pb[q] = (a.mode == 0) ? a.Pbar[q * a.cs + cc] : v[q];
     if (a.mode == 0) a.Pbar[q * a.cs + cc] = 0.0;
   }
-  // (dS/dP)^T v by reverse mode, then dU/dP by forward-mode dual numbers, one
-  // tangent (primitive) per pass; the passes are real loop iterations so only
-  // one pass's dual numbers are live at a time (two waves per SIMD fit).
+  // (dS/dP)^T v by reverse mode, then dU/dP written out, then the transposed
+  // solve (implicit-function theorem for con2prim).
   if (a.mode == 0) {
     MetricDeriv md;
     metric_deriv<SHIFT>(cv, 0u, 2u, 4u, bx.inv_dx, md);
     sources_vjp<SHIFT>(cm, md, P, a.ph.gam, v, pb);
   }
-  constexpr int NU = 1;
   double J[5][8];
-#pragma clang loop unroll(disable)
-  for (int h = 0; h < 8 / NU; ++h) {
-    DN<NU> Pd[8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      Pd[q] = DN<NU>(P[q]);
-#pragma unroll
-      for (int t = 0; t < NU; ++t) Pd[q].d[t] = (q == NU * h + t) ? 1.0 : 0.0;
-    }
-    DN<NU> U[8];
-    p2c_cell(cm.g, cm.sqrtg, a.ph.gm1, Pd, U);
-#pragma unroll
-    for (int r = 0; r < 5; ++r)
-#pragma unroll
-      for (int c = 0; c < 8; ++c)
-        if (c / NU == h) J[r][c] = U[r].d[c % NU];
-  }
+  p2c_jacobian(cm.g, cm.sqrtg, a.ph.gm1, P, J);
   double w[8];
   solve_dUdP_T(J, cm.sqrtg, pb, w);
   if (a.mode == 1) {

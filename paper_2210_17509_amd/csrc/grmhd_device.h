@@ -307,21 +307,13 @@ template <typename R> __device__ __forceinline__ R minmod(R a, R b) {
   return (a * b <= R(0)) ? R(0) : (rabs(a) < rabs(b) ? a : b);
 }
 
-// WENO5 value at the right face of the centre cell c of (a, b, c, d, e)
-// [Shu 98]: Jiang-Shu weights d_k / (eps + beta_k)^2 (ZW = false) or Borges
-// WENO-Z weights d_k (1 + (|beta_0 - beta_2| / (beta_k + eps))^p) (ZW = true).
-// The normalisation is folded into a single division.
-// ZPC = 1 or 2 fixes the WENO-Z exponent at compile time; ZPC = 0 takes it from zp.
-template <bool ZW, int ZPC = 0, typename R>
-__device__ __forceinline__ R weno5(R a, R b, R c, R d, R e, R eps, int zp) {
-  if (ZPC != 0) zp = ZPC;
-  const R q0 = R(2) * a - R(7) * b + R(11) * c;  // x6
-  const R q1 = -b + R(5) * c + R(2) * d;
-  const R q2 = R(2) * c + R(5) * d - e;
-  const R b0 = R(13.0 / 12.0) * rsq(a - R(2) * b + c) + R(0.25) * rsq(a - R(4) * b + R(3) * c);
-  const R b1 = R(13.0 / 12.0) * rsq(b - R(2) * c + d) + R(0.25) * rsq(b - d);
-  const R b2 = R(13.0 / 12.0) * rsq(c - R(2) * d + e) + R(0.25) * rsq(R(3) * c - R(4) * d + e);
-  R w0, w1, w2;
+// Un-normalised WENO5 weights from the smoothness indicators [Shu 98]:
+// Jiang-Shu d_k / (eps + beta_k)^2 (ZW = false) or Borges WENO-Z
+// d_k (1 + (|beta_0 - beta_2| / (beta_k + eps))^p) (ZW = true), each multiplied
+// by a common positive factor (which the normalisation removes) so that no
+// division is needed in FP64.
+template <bool ZW, typename R>
+__device__ __forceinline__ void weno5_weights(R b0, R b1, R b2, R eps, int zp, R& w0, R& w1, R& w2) {
   if (!ZW) {
     const R t0 = rsq(eps + b0), t1 = rsq(eps + b1), t2 = rsq(eps + b2);
     w0 = R(0.1) * (t1 * t2);
@@ -349,9 +341,63 @@ __device__ __forceinline__ R weno5(R a, R b, R c, R d, R e, R eps, int zp) {
       w2 = R(0.3) * (R(1) + r2);
     }
   }
+}
+
+// WENO5 value at the right face of the centre cell c of (a, b, c, d, e).
+// ZPC = 1 or 2 fixes the WENO-Z exponent at compile time; ZPC = 0 takes it from zp.
+template <bool ZW, int ZPC = 0, typename R>
+__device__ __forceinline__ R weno5(R a, R b, R c, R d, R e, R eps, int zp) {
+  if (ZPC != 0) zp = ZPC;
+  const R q0 = R(2) * a - R(7) * b + R(11) * c;  // x6
+  const R q1 = -b + R(5) * c + R(2) * d;
+  const R q2 = R(2) * c + R(5) * d - e;
+  const R b0 = R(13.0 / 12.0) * rsq(a - R(2) * b + c) + R(0.25) * rsq(a - R(4) * b + R(3) * c);
+  const R b1 = R(13.0 / 12.0) * rsq(b - R(2) * c + d) + R(0.25) * rsq(b - d);
+  const R b2 = R(13.0 / 12.0) * rsq(c - R(2) * d + e) + R(0.25) * rsq(R(3) * c - R(4) * d + e);
+  R w0, w1, w2;
+  weno5_weights<ZW>(b0, b1, b2, eps, zp, w0, w1, w2);
   // An IEEE division: the refined hardware reciprocal used elsewhere reproduces this
   // quotient in isolation, but gave wrong stage-kernel results in this position.
   return (w0 * q0 + w1 * q1 + w2 * q2) / (R(6) * (w0 + w1 + w2));
+}
+
+// Both WENO5 values at the face between cells s[2] and s[3] of the six-cell
+// stencil s[0..5]: PL from (s0, .., s4), PR from the mirrored (s5, .., s1).
+// The two sides share two of their three candidate values (q1 of one side is q2
+// of the other) and two of their three second differences (those over cells
+// 1..3 and 2..4).  In FP64 one IEEE division serves both normalisations while
+// the product of the two denominators stays well inside the exponent range
+// (not for WENO-Z with p = 2, whose denominators can reach 1e-240).
+template <bool ZW, int ZPC = 0, typename R>
+__device__ __forceinline__ void weno5_lr(const R* s, R eps, int zp, R& PL, R& PR) {
+  if (ZPC != 0) zp = ZPC;
+  const R qa = R(2) * s[0] - R(7) * s[1] + R(11) * s[2];  // x6: q0 of L
+  const R qb = -s[1] + R(5) * s[2] + R(2) * s[3];          // q1 of L, q2 of R
+  const R qc = R(2) * s[2] + R(5) * s[3] - s[4];           // q2 of L, q1 of R
+  const R qd = R(2) * s[5] - R(7) * s[4] + R(11) * s[3];  // q0 of R
+  const R c13 = R(13.0 / 12.0);
+  const R E1 = c13 * rsq(s[1] - R(2) * s[2] + s[3]);
+  const R E2 = c13 * rsq(s[2] - R(2) * s[3] + s[4]);
+  const R bL0 = c13 * rsq(s[0] - R(2) * s[1] + s[2]) + R(0.25) * rsq(s[0] - R(4) * s[1] + R(3) * s[2]);
+  const R bL1 = E1 + R(0.25) * rsq(s[1] - s[3]);
+  const R bL2 = E2 + R(0.25) * rsq(R(3) * s[2] - R(4) * s[3] + s[4]);
+  const R bR0 = c13 * rsq(s[5] - R(2) * s[4] + s[3]) + R(0.25) * rsq(s[5] - R(4) * s[4] + R(3) * s[3]);
+  const R bR1 = E2 + R(0.25) * rsq(s[4] - s[2]);
+  const R bR2 = E1 + R(0.25) * rsq(R(3) * s[3] - R(4) * s[2] + s[1]);
+  R l0, l1, l2, r0, r1, r2;
+  weno5_weights<ZW>(bL0, bL1, bL2, eps, zp, l0, l1, l2);
+  weno5_weights<ZW>(bR0, bR1, bR2, eps, zp, r0, r1, r2);
+  const R nL = l0 * qa + l1 * qb + l2 * qc, dL = R(6) * (l0 + l1 + l2);
+  const R nR = r0 * qd + r1 * qc + r2 * qb, dR = R(6) * (r0 + r1 + r2);
+  const R prod = dL * dR;
+  if (sizeof(R) == 8 && !(ZW && zp == 2) && prod > R(1e-300) && prod < R(1e300)) {
+    const R inv = R(1) / prod;
+    PL = nL * (dR * inv);
+    PR = nR * (dL * inv);
+  } else {
+    PL = nL / dL;
+    PR = nR / dR;
+  }
 }
 
 // ---------------------------------------------------------------- HLLE
