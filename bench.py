@@ -185,6 +185,47 @@ def hbm_summary(args):
     print("\n".join(lines))
 
 
+SQ_PASSES = (
+    "SQ_WAVES SQ_INSTS_VALU SQ_ACTIVE_INST_VALU SQ_WAVE_CYCLES SQ_WAIT_INST_ANY SQ_BUSY_CYCLES SQ_WAIT_ANY "
+    "SQ_ACTIVE_INST_ANY",
+    "SQ_INSTS_VMEM_RD SQ_INST_LEVEL_VMEM SQ_INSTS_LDS SQ_LDS_BANK_CONFLICT SQ_INSTS_SALU SQ_INSTS_VALU_CVT "
+    "SQ_INSTS_VALU_TRANS_F32 SQ_INSTS_VALU_TRANS_F64",
+)
+
+
+def sq_summary(args):
+    """Write profiles/k_stage_<workload>_sq.txt from the two rocprofv3 --pmc runs of SQ_PASSES."""
+    dirs = args.sq_summary
+    means, kernel, ndisp = {}, None, None
+    for d, names in zip(dirs, SQ_PASSES):
+        for c in names.split():
+            rows = _counter_rows(d, c, "k_stage")
+            kernel = kernel or rows[0][0]
+            ndisp = len(rows)
+            means[c] = sum(v for _, v in rows) / len(rows)
+    waves = means["SQ_WAVES"]
+    run = (f"--output-format csv -d {{}} -o bench -- python bench.py --workload {args.workload} --steps 1 "
+           "--warmup 0 --no-cpu-baseline --no-adjoint")
+    lines = [f"# SQ counters of the stage kernel (con2prim included), workload: {WORKLOADS[args.workload]['desc']}",
+             f"# (mean over the {ndisp} stage dispatches of one step; *_CYCLES and ACTIVE/WAIT counters in "
+             "quad-cycles, summed over SEs)",
+             "# Commands (repository root, one MI355X):",
+             f"#   rocprofv3 --pmc {SQ_PASSES[0]} " + run.format("S1"),
+             f"#   rocprofv3 --pmc {SQ_PASSES[1]} " + run.format("S2"),
+             f"#   python bench.py --workload {args.workload} --sq-summary S1 S2",
+             f"kernel_source_sha256: {kernel_source_hash()}",
+             f"kernel: {kernel}"]
+    for c in sorted(means):
+        lines.append(f"{c}: {means[c]:.4e}  ({means[c] / waves:.1f} per wave)")
+    lines.append("waiting share of wave cycles (SQ_WAIT_ANY / SQ_WAVE_CYCLES): "
+                 f"{means['SQ_WAIT_ANY'] / means['SQ_WAVE_CYCLES']:.3f}")
+    path = os.path.join(ROOT, "profiles", f"k_stage_{args.workload}_sq.txt")
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    with open(path, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def stats_summary(args):
     """Write profiles/kernels_<workload>_stats.txt from a rocprofv3 --kernel-trace --stats folder."""
     import csv
@@ -195,7 +236,12 @@ def stats_summary(args):
         raise SystemExit(f"no kernel_stats.csv under {d}")
     with open(files[0]) as fh:
         rows = list(csv.DictReader(fh))
-    lines = [f"# rocprofv3 kernel statistics, workload: {WORKLOADS[args.workload]['desc']}",
+    if args.adjoint:
+        name, desc = "adjoint128", ("adjoint, flat 128^3 smooth, WENO5-Z, 10 SSPRK3 steps with stage checkpoints, "
+                                    "then 10 adjoint steps (FP64)")
+    else:
+        name, desc = args.workload, WORKLOADS[args.workload]["desc"]
+    lines = [f"# rocprofv3 kernel statistics, workload: {desc}",
              "# Command (repository root, one MI355X):",
              f"#   {cmd}",
              f"kernel_source_sha256: {kernel_source_hash()}",
@@ -203,7 +249,7 @@ def stats_summary(args):
     for r in rows[:12]:
         lines.append(f"{int(r['Calls']):6d} {float(r['AverageNs']) / 1e6:10.4f} {float(r['MinNs']) / 1e6:10.4f} "
                      f"{float(r['MaxNs']) / 1e6:10.4f} {float(r['Percentage']):7.2f}  {r['Name'][:150]}")
-    path = os.path.join(ROOT, "profiles", f"kernels_{args.workload}_stats.txt")
+    path = os.path.join(ROOT, "profiles", f"kernels_{name}_stats.txt")
     os.makedirs(os.path.dirname(path), exist_ok=True)
     with open(path, "w") as fh:
         fh.write("\n".join(lines) + "\n")
@@ -344,7 +390,10 @@ def main():
     ap.add_argument("--hbm-summary", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
                     help="write profiles/k_stage_<workload>_hbm.txt from rocprofv3 --pmc output folders")
     ap.add_argument("--stats-summary", nargs=2, metavar=("STATS_DIR", "COMMAND"),
-                    help="write profiles/kernels_<workload>_stats.txt from a rocprofv3 --stats folder")
+                    help="write profiles/kernels_<workload>_stats.txt (with --adjoint: kernels_adjoint128_stats.txt) "
+                         "from a rocprofv3 --stats folder")
+    ap.add_argument("--sq-summary", nargs=2, metavar=("SQ_PASS1_DIR", "SQ_PASS2_DIR"),
+                    help="write profiles/k_stage_<workload>_sq.txt from the two rocprofv3 --pmc SQ passes")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -352,6 +401,8 @@ def main():
         return hbm_summary(args)
     if args.stats_summary:
         return stats_summary(args)
+    if args.sq_summary:
+        return sq_summary(args)
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU: this build has no multi-GPU path (asked for {args.gpus})",
               file=sys.stderr)

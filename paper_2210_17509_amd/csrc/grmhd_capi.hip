@@ -247,8 +247,15 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int tg,
   const int b = find_box(a.tab.tile_prefix + TI * (a.tab.nbox + 1), a.tab.nbox, tg);
   const KBox& bx = a.tab.box[b];
   const int t = tg - a.tab.tile_prefix[TI * (a.tab.nbox + 1) + b];
-  const int ntx = (bx.n[0] + TX - 1) / TX, nty = (bx.n[1] + TY - 1) / TY;
-  const int org[3] = {(t % ntx) * TX, ((t / ntx) % nty) * TY, (t / (ntx * nty)) * TZ};
+  // Tile walk: x fastest, then y within a strip of SH tile rows, then z, then
+  // the next strip.  A contiguous run of tiles (one XCD's share) thus marches
+  // up z through a strip about as wide as the tiles one XCD holds at once, so
+  // the z-halo rows a tile layer loads are still in that XCD's L2 when the
+  // next layer needs them as its own cells.
+  const int ntx = (bx.n[0] + TX - 1) / TX, nty = (bx.n[1] + TY - 1) / TY, ntz = (bx.n[2] + TZ - 1) / TZ;
+  const int SH = max(1, min(nty, 128 / ntx));
+  const int r = t / ntx, st = r / (SH * ntz), h = min(SH, nty - st * SH), r3 = r - st * SH * ntz;
+  const int org[3] = {(t % ntx) * TX, (st * SH + r3 % h) * TY, (r3 / h) * TZ};
   const int tid = threadIdx.x;
   const int l[3] = {tid % TX, (tid / TX) % TY, tid / (TX * TY)};
   const int i = org[0] + l[0], j = org[1] + l[1], k = org[2] + l[2];
@@ -762,7 +769,9 @@ struct AdjCellArgs {
   int64_t cs, vs;
   KPhys ph;
   double cstage, dt;
-  int32_t first_stage;
+  double* Pout;                   // stage 0 only (else null): receives the checkpointed primitives of U^n
+  int32_t first_stage;            // stage 0: its adjoint adds to Gn, and P-bar is left as is
+  int32_t gn_init;                // Gn is written, not accumulated (first stage processed)
   int32_t mode;  // 0: RK stage adjoint; 1: con2prim adjoint only (V = gP in, Gn = gU out)
 };
 
@@ -787,7 +796,16 @@ __global__ __launch_bounds__(C2P_BLOCK) __attribute__((amdgpu_waves_per_eu(2))) 
     P[q] = a.P[q * a.cs + cc];
     v[q] = a.Vin[q * a.cs + cc];
     pb[q] = (a.mode == 0) ? a.Pbar[q * a.cs + cc] : v[q];
-    if (a.mode == 0) a.Pbar[q * a.cs + cc] = 0.0;
+  }
+  // stores only after every load (the pointers may alias as far as the
+  // compiler knows, so a store would hold back the loads behind it)
+  if (a.mode == 0 && !a.first_stage) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) a.Pbar[q * a.cs + cc] = 0.0;
+  }
+  if (a.Pout) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) a.Pout[q * a.cs + cc] = P[q];
   }
   // (dS/dP)^T v by reverse mode, then dU/dP written out, then the transposed
   // solve (implicit-function theorem for con2prim).
@@ -806,10 +824,13 @@ __global__ __launch_bounds__(C2P_BLOCK) __attribute__((amdgpu_waves_per_eu(2))) 
     return;
   }
   const double cs = a.cstage;
+  double gp[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) gp[q] = a.gn_init ? 0.0 : a.Gn[q * a.cs + cc];
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
     const double gs = cs * (v[q] + a.dt * w[q]);
-    double gn = a.Gn[q * a.cs + cc] + (1.0 - cs) * v[q];
+    double gn = gp[q] + (1.0 - cs) * v[q];
     if (a.first_stage) gn += gs;
     else a.V[q * a.cs + cc] = gs;
     a.Gn[q * a.cs + cc] = gn;
@@ -823,16 +844,6 @@ __global__ __launch_bounds__(C2P_BLOCK) void k_fill(Table tab, double* X, int64_
   const int64_t cc = tab.box[b].cell_off + c;
 #pragma unroll
   for (int q = 0; q < 8; ++q) X[q * cs + cc] = val;
-}
-
-// Copy the interior cells of 8 pooled fields.
-__global__ __launch_bounds__(C2P_BLOCK) void k_copy(Table tab, const double* __restrict__ X, double* __restrict__ Y,
-                                                     int64_t cs) {
-  int b, c, vb;
-  if (!cell_of(tab, blockIdx.x, threadIdx.x, b, c, vb)) return;
-  const int64_t cc = tab.box[b].cell_off + c;
-#pragma unroll
-  for (int q = 0; q < 8; ++q) Y[q * cs + cc] = X[q * cs + cc];
 }
 
 // ---------------------------------------------------------------- host side
@@ -1386,7 +1397,9 @@ int grmhd_con2prim_adjoint(const grmhd_domain* dom, const grmhd_params* par, con
   a.ph = ph;
   a.cstage = 1.0;
   a.dt = 0.0;
+  a.Pout = nullptr;
   a.first_stage = 0;
+  a.gn_init = 0;
   a.mode = 1;
   hipError_t e = launch_adj_cell(a, pr, static_cast<hipStream_t>(stream));
   return e == hipSuccess ? GRMHD_OK : fail_hip(e, "k_adj_cell");
@@ -1418,9 +1431,9 @@ int grmhd_rk_step_adjoint(const grmhd_domain* dom, const grmhd_params* par, cons
   double* Pbar = V + fsz;
   const Table tab = make_table(dom);
   const unsigned cb = (unsigned)pr.c2p_blocks;
-  // P-bar starts at zero; each stage's cell kernel clears it again after use
+  // P-bar starts at zero; the cell kernels of the later stages clear it again
+  // after use.  gU_in is written by the first stage processed, then accumulated.
   hipLaunchKernelGGL(k_fill, dim3(cb), dim3(C2P_BLOCK), 0, s, tab, Pbar, dom->cell_stride, 0.0);
-  hipLaunchKernelGGL(k_fill, dim3(cb), dim3(C2P_BLOCK), 0, s, tab, gU_in, dom->cell_stride, 0.0);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail_hip(e, "adjoint setup");
   for (int st = nst - 1; st >= 0; --st) {
@@ -1456,14 +1469,14 @@ int grmhd_rk_step_adjoint(const grmhd_domain* dom, const grmhd_params* par, cons
     a.ph = ph;
     a.cstage = cst[st];
     a.dt = dt;
+    a.Pout = (st == 0) ? P : nullptr;
     a.first_stage = (st == 0);
+    a.gn_init = (st == nst - 1);
     a.mode = 0;
     e = launch_adj_cell(a, pr, s);
     if (e != hipSuccess) return fail_hip(e, "k_adj_cell");
   }
-  hipLaunchKernelGGL(k_copy, dim3(cb), dim3(C2P_BLOCK), 0, s, tab, stage_ckpt, P, dom->cell_stride);
-  e = hipGetLastError();
-  return e == hipSuccess ? GRMHD_OK : fail_hip(e, "adjoint P");
+  return GRMHD_OK;
 }
 
 int grmhd_timing_enable(int32_t on) {
