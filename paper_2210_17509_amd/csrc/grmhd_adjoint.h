@@ -289,13 +289,13 @@ __device__ __forceinline__ void sources_vjp(const CentreMetric& m, const MetricD
 
 // ---------------------------------------------------------------- reconstruction gradients
 
-// WENO5 value at the right face of c in (a, b, c, d, e) and its gradient with
-// respect to (a, b, c, d, e).  The weights are differentiated in their
-// un-normalised product form (JS: d_k prod_{j != k} (eps + beta_j)^2; Z:
-// d_k (e_k^p + tau^p) prod_{j != k} e_j^p, e = beta + eps, tau = |beta_0 - beta_2|),
-// which normalises to the forward kernel's weights.
+// Adjoint of the WENO5 value at the right face of c in (a, b, c, d, e): g[o] =
+// ab * d(value)/d(s_o).  Reverse mode through the normalisation and through
+// the weights in their un-normalised product form (JS: d_k prod_{j != k}
+// (eps + beta_j)^2; Z: d_k (e_k^p + tau^p) prod_{j != k} e_j^p, e = beta + eps,
+// tau = |beta_0 - beta_2|), which normalises to the forward kernel's weights.
 template <bool ZW, int ZPC = 0>
-__device__ __forceinline__ double weno5_grad(const double* s, double eps, int zp, double g[5]) {
+__device__ __forceinline__ void weno5_vjp(const double* s, double eps, int zp, double ab, double g[5]) {
   if (ZPC != 0) zp = ZPC;  // exponent fixed at compile time
   const double a = s[0], b = s[1], c = s[2], d = s[3], e = s[4];
   const double q[3] = {2 * a - 7 * b + 11 * c, -b + 5 * c + 2 * d, 2 * c + 5 * d - e};
@@ -305,72 +305,74 @@ __device__ __forceinline__ double weno5_grad(const double* s, double eps, int zp
   const double be[3] = {13.0 / 12.0 * X0 * X0 + 0.25 * Y0 * Y0, 13.0 / 12.0 * X1 * X1 + 0.25 * Y1 * Y1,
                         13.0 / 12.0 * X2 * X2 + 0.25 * Y2 * Y2};
   const double dk[3] = {0.1, 0.6, 0.3};
-  double w[3], dw[3][3];  // dw[k][m] = d w_k / d beta_m
+  // forward: un-normalised weights and the pieces their adjoint needs
+  double w[3], t[3], f[3], tpd = 0.0, sg = 0.0;
   if (!ZW) {
-    double t[3], tp[3];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      t[k] = (eps + be[k]) * (eps + be[k]);
-      tp[k] = 2.0 * (eps + be[k]);
-    }
+    for (int k = 0; k < 3; ++k) t[k] = (eps + be[k]) * (eps + be[k]);
     w[0] = dk[0] * t[1] * t[2];
     w[1] = dk[1] * t[0] * t[2];
     w[2] = dk[2] * t[0] * t[1];
-    dw[0][0] = 0.0;                 dw[0][1] = dk[0] * tp[1] * t[2]; dw[0][2] = dk[0] * t[1] * tp[2];
-    dw[1][0] = dk[1] * tp[0] * t[2]; dw[1][1] = 0.0;                 dw[1][2] = dk[1] * t[0] * tp[2];
-    dw[2][0] = dk[2] * tp[0] * t[1]; dw[2][1] = dk[2] * t[0] * tp[1]; dw[2][2] = 0.0;
   } else {
     const double tau = fabs(be[0] - be[2]);
-    const double sg = (be[0] > be[2]) ? 1.0 : ((be[0] < be[2]) ? -1.0 : 0.0);
-    const double dtau[3] = {sg, 0.0, -sg};
-    double ep[3], epd[3];  // e^p and d(e^p)/de
-    double e_[3];
+    sg = (be[0] > be[2]) ? 1.0 : ((be[0] < be[2]) ? -1.0 : 0.0);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      e_[k] = be[k] + eps;
-      ep[k] = (zp == 2) ? e_[k] * e_[k] : e_[k];
-      epd[k] = (zp == 2) ? 2.0 * e_[k] : 1.0;
+      const double ek = be[k] + eps;
+      t[k] = (zp == 2) ? ek * ek : ek;  // e_k^p
     }
     const double tp = (zp == 2) ? tau * tau : tau;
-    const double tpd = (zp == 2) ? 2.0 * tau : 1.0;
+    tpd = (zp == 2) ? 2.0 * tau : 1.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      f[k] = t[k] + tp;
+      w[k] = dk[k] * f[k] * t[(k + 1) % 3] * t[(k + 2) % 3];
+    }
+  }
+  const double i6W = 1.0 / (6.0 * (w[0] + w[1] + w[2]));
+  const double qv = (w[0] * q[0] + w[1] * q[1] + w[2] * q[2]) * i6W;
+  // reverse: value -> weights -> e_k^p (or (eps + beta_k)^2) -> beta_k
+  double wb[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) wb[k] = ab * (q[k] - 6.0 * qv) * i6W * dk[k];  // adjoint of w_k / d_k
+  double bb[3];
+  if (!ZW) {
+    const double tb0 = wb[1] * t[2] + wb[2] * t[1];
+    const double tb1 = wb[0] * t[2] + wb[2] * t[0];
+    const double tb2 = wb[0] * t[1] + wb[1] * t[0];
+    bb[0] = 2.0 * (eps + be[0]) * tb0;
+    bb[1] = 2.0 * (eps + be[1]) * tb1;
+    bb[2] = 2.0 * (eps + be[2]) * tb2;
+  } else {
+    // w_k / d_k = f_k t_j t_l with f_k = t_k + tau^p
+    double tb[3] = {0.0, 0.0, 0.0}, tpb = 0.0;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       const int j = (k + 1) % 3, l = (k + 2) % 3;
-      const double f = ep[k] + tp;
-      const double gk = ep[j] * ep[l];
-      w[k] = dk[k] * f * gk;
-#pragma unroll
-      for (int m = 0; m < 3; ++m) {
-        double df = tpd * dtau[m] + (m == k ? epd[k] : 0.0);
-        double dg = (m == j) ? epd[j] * ep[l] : ((m == l) ? ep[j] * epd[l] : 0.0);
-        dw[k][m] = dk[k] * (df * gk + f * dg);
-      }
+      const double fb = wb[k] * t[j] * t[l];
+      const double wf = wb[k] * f[k];
+      tb[k] += fb;
+      tpb += fb;
+      tb[j] += wf * t[l];
+      tb[l] += wf * t[j];
     }
+    const double taub = tpb * tpd;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) bb[k] = (zp == 2) ? 2.0 * (be[k] + eps) * tb[k] : tb[k];
+    bb[0] += sg * taub;
+    bb[2] -= sg * taub;
   }
-  const double W = w[0] + w[1] + w[2];
-  const double i6W = 1.0 / (6.0 * W);
-  const double qv = (w[0] * q[0] + w[1] * q[1] + w[2] * q[2]) * i6W;
-  // d qv / d w_k and d qv / d beta_m
-  double cw[3], cb[3];
-#pragma unroll
-  for (int k = 0; k < 3; ++k) cw[k] = (q[k] - 6.0 * qv) * i6W;
-#pragma unroll
-  for (int m = 0; m < 3; ++m) cb[m] = cw[0] * dw[0][m] + cw[1] * dw[1][m] + cw[2] * dw[2][m];
-  const double o0 = w[0] * i6W, o1 = w[1] * i6W, o2 = w[2] * i6W;
+  // beta_m = 13/12 X_m^2 + 1/4 Y_m^2, and the candidates q_k, are linear in the stencil
+  const double xb0 = 13.0 / 6.0 * X0 * bb[0], yb0 = 0.5 * Y0 * bb[0];
+  const double xb1 = 13.0 / 6.0 * X1 * bb[1], yb1 = 0.5 * Y1 * bb[1];
+  const double xb2 = 13.0 / 6.0 * X2 * bb[2], yb2 = 0.5 * Y2 * bb[2];
+  const double o0 = ab * w[0] * i6W, o1 = ab * w[1] * i6W, o2 = ab * w[2] * i6W;
   // candidates: q0 = (2, -7, 11, 0, 0), q1 = (0, -1, 5, 2, 0), q2 = (0, 0, 2, 5, -1)
-  g[0] = 2 * o0;
-  g[1] = -7 * o0 - o1;
-  g[2] = 11 * o0 + 5 * o1 + 2 * o2;
-  g[3] = 2 * o1 + 5 * o2;
-  g[4] = -o2;
-  // smoothness indicators
-  const double k13 = 13.0 / 6.0;
-  g[0] += cb[0] * (k13 * X0 + 0.5 * Y0);
-  g[1] += cb[0] * (-2 * k13 * X0 - 2.0 * Y0) + cb[1] * (k13 * X1 + 0.5 * Y1);
-  g[2] += cb[0] * (k13 * X0 + 1.5 * Y0) + cb[1] * (-2 * k13 * X1) + cb[2] * (k13 * X2 + 1.5 * Y2);
-  g[3] += cb[1] * (k13 * X1 - 0.5 * Y1) + cb[2] * (-2 * k13 * X2 - 2.0 * Y2);
-  g[4] += cb[2] * (k13 * X2 + 0.5 * Y2);
-  return qv;
+  g[0] = 2 * o0 + xb0 + yb0;
+  g[1] = -7 * o0 - o1 - 2 * xb0 - 4 * yb0 + xb1 + yb1;
+  g[2] = 11 * o0 + 5 * o1 + 2 * o2 + xb0 + 3 * yb0 - 2 * xb1 + xb2 + 3 * yb2;
+  g[3] = 2 * o1 + 5 * o2 + xb1 - yb1 - 2 * xb2 - 4 * yb2;
+  g[4] = -o2 + xb2 + yb2;
 }
 
 // minmod left state s[2] + mm(s[2]-s[1], s[3]-s[2]) / 2 and its gradient w.r.t. s[1..3]

@@ -672,16 +672,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
       double g5[5];
       if (fbL) sb[2] += aL;
       else {
-        weno5_grad<ZW, ZP>(s, eps, ZP, g5);
+        weno5_vjp<ZW, ZP>(s, eps, ZP, aL, g5);
 #pragma unroll
-        for (int o = 0; o < 5; ++o) sb[o] += aL * g5[o];
+        for (int o = 0; o < 5; ++o) sb[o] += g5[o];
       }
       if (fbR) sb[3] += aR;
       else {
         const double sr[5] = {s[5], s[4], s[3], s[2], s[1]};
-        weno5_grad<ZW, ZP>(sr, eps, ZP, g5);
+        weno5_vjp<ZW, ZP>(sr, eps, ZP, aR, g5);
 #pragma unroll
-        for (int o = 0; o < 5; ++o) sb[5 - o] += aR * g5[o];
+        for (int o = 0; o < 5; ++o) sb[5 - o] += g5[o];
       }
     }
     if (D == 0) {
