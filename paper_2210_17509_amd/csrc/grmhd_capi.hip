@@ -479,12 +479,16 @@ template <int D, int RECON, bool SHIFT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_adj_face(AdjArgs a) {
   const int nb = a.tab.nbox;
   const int32_t* pre = a.tab.face_prefix + D * (nb + 1);
-  const int b = find_box(pre, nb, blockIdx.x);
+  // y faces: each XCD takes a contiguous run of face blocks, so the blocks of
+  // neighbouring grid rows (overlapping stencils) share its L2 (timed: no gain
+  // for x faces, a loss for z faces)
+  const int blk = (D == 1) ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+  const int b = find_box(pre, nb, blk);
   const KBox& bx = a.tab.box[b];
   const int nfx = bx.n[0] + (D == 0), nfy = bx.n[1] + (D == 1), nfz = bx.n[2] + (D == 2);
   // Lanes past the box's last face take part (with nothing to add) in the
   // wave-level exchange of the x faces below.
-  const int lin_raw = (blockIdx.x - pre[b]) * FACE_BLOCK + threadIdx.x;
+  const int lin_raw = (blk - pre[b]) * FACE_BLOCK + threadIdx.x;
   const bool live = lin_raw < nfx * nfy * nfz;
   const int lin = live ? lin_raw : 0;
   const int i = lin % nfx;
