@@ -782,18 +782,22 @@ struct AdjCellArgs {
 // Cell part of the stage adjoint: source VJP, con2prim through the implicit-
 // function theorem, and the transposed stage combine
 // U_{s+1} = (1 - c) U^n + c U_s + c dt L(U_s).
+// Waves per SIMD: three fit the zero-shift variant without spills (156 VGPRs),
+// the shift variant needs the register budget of two.
 template <bool SHIFT>
-__global__ __launch_bounds__(C2P_BLOCK) __attribute__((amdgpu_waves_per_eu(2))) void k_adj_cell(AdjCellArgs a) {
+__global__ __launch_bounds__(C2P_BLOCK) __attribute__((amdgpu_waves_per_eu(SHIFT ? 2 : 3))) void k_adj_cell(
+    AdjCellArgs a) {
   int b, c, vb;
   if (!cell_of(a.tab, blockIdx.x, threadIdx.x, b, c, vb)) return;
   const KBox& bx = a.tab.box[b];
   const int64_t cc = bx.cell_off + c;
-  // the cell's 8 vertices, loaded once for the centre metric and its derivatives
-  CornerVerts<SHIFT ? 10 : 7> cv;
-  cv.load(GlobalVerts{a.alpha + bx.vert_off, SHIFT ? a.beta + bx.vert_off : nullptr, a.gamma + bx.vert_off, a.vs},
-          vb, bx.VX, bx.VXY);
+  // centre metric (and for the stage adjoint its derivatives) first, one vertex
+  // field at a time, before the cell's own fields are loaded
+  const GlobalVerts gv{a.alpha + bx.vert_off, SHIFT ? a.beta + bx.vert_off : nullptr, a.gamma + bx.vert_off, a.vs};
   CentreMetric cm;
-  centre_metric<SHIFT, true>(cv, 0u, 2u, 4u, cm);
+  MetricDeriv md;
+  if (a.mode == 0) centre_metric_deriv<SHIFT>(gv, vb, bx.VX, bx.VXY, bx.inv_dx, cm, md);
+  else centre_metric<false, false>(gv, vb, bx.VX, bx.VXY, cm);
   double P[8], v[8], pb[8];
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
@@ -813,11 +817,7 @@ __global__ __launch_bounds__(C2P_BLOCK) __attribute__((amdgpu_waves_per_eu(2))) 
   }
   // (dS/dP)^T v by reverse mode, then dU/dP written out, then the transposed
   // solve (implicit-function theorem for con2prim).
-  if (a.mode == 0) {
-    MetricDeriv md;
-    metric_deriv<SHIFT>(cv, 0u, 2u, 4u, bx.inv_dx, md);
-    sources_vjp<SHIFT>(cm, md, P, a.ph.gam, v, pb);
-  }
+  if (a.mode == 0) sources_vjp<SHIFT>(cm, md, P, a.ph.gam, v, pb);
   double J[5][8];
   p2c_jacobian(cm.g, cm.sqrtg, a.ph.gm1, P, J);
   double w[8];

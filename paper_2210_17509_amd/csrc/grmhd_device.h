@@ -152,21 +152,6 @@ template <int STRIDE> struct LdsVerts {
   __device__ __forceinline__ double operator()(int f, uint32_t v) const { return s[f * STRIDE + v]; }
 };
 
-// The 8 vertices of one cell held in registers: field f of corner
-// dx + 2 dy + 4 dz at index dx + 2 dy + 4 dz (corner strides 1, 2, 4).
-template <int NF> struct CornerVerts {
-  double v[NF][8];
-  template <typename V>
-  __device__ __forceinline__ void load(const V& vt, uint32_t vb, uint32_t VX, uint32_t VXY) {
-    const uint32_t o[8] = {0u, 1u, VX, VX + 1u, VXY, VXY + 1u, VXY + VX, VXY + VX + 1u};
-#pragma unroll
-    for (int f = 0; f < NF; ++f)
-#pragma unroll
-      for (int c = 0; c < 8; ++c) v[f][c] = vt(f, vb + o[c]);
-  }
-  __device__ __forceinline__ double operator()(int f, uint32_t c) const { return v[f][c]; }
-};
-
 // ---------------------------------------------------------------- face metric
 
 template <typename R> struct FaceMetric {
@@ -433,6 +418,22 @@ struct CentreMetric {
   double alpha, beta[3], g[6], gi[6], sqrtg;
 };
 
+// Inverse spatial metric and sqrt(gamma) from the centre gamma_ij.
+__device__ __forceinline__ void centre_inverse(CentreMetric& m) {
+  const double* g = m.g;
+  const double cxx = g[3] * g[5] - g[4] * g[4];
+  const double cxy = g[2] * g[4] - g[1] * g[5];
+  const double cxz = g[1] * g[4] - g[2] * g[3];
+  const double cyy = g[0] * g[5] - g[2] * g[2];
+  const double cyz = g[1] * g[2] - g[0] * g[4];
+  const double czz = g[0] * g[3] - g[1] * g[1];
+  const double det = g[0] * cxx + g[1] * cxy + g[2] * cxz;
+  const double id = 1.0 / det;
+  m.gi[0] = cxx * id; m.gi[1] = cxy * id; m.gi[2] = cxz * id;
+  m.gi[3] = cyy * id; m.gi[4] = cyz * id; m.gi[5] = czz * id;
+  m.sqrtg = sqrt(det);
+}
+
 // Cell-centre metric: mean of the cell's 8 vertices; inverse and sqrt(gamma)
 // from the averaged gamma_ij.
 template <bool SHIFT, bool NEED_ALPHA, typename V>
@@ -448,18 +449,7 @@ __device__ __forceinline__ void centre_metric(const V& vt, uint32_t vb, uint32_t
   m.alpha = NEED_ALPHA ? avg(VF_ALPHA) : 1.0;
 #pragma unroll
   for (int q = 0; q < 3; ++q) m.beta[q] = SHIFT ? avg(VF_BETA + q) : 0.0;
-  const double* g = m.g;
-  const double cxx = g[3] * g[5] - g[4] * g[4];
-  const double cxy = g[2] * g[4] - g[1] * g[5];
-  const double cxz = g[1] * g[4] - g[2] * g[3];
-  const double cyy = g[0] * g[5] - g[2] * g[2];
-  const double cyz = g[1] * g[2] - g[0] * g[4];
-  const double czz = g[0] * g[3] - g[1] * g[1];
-  const double det = g[0] * cxx + g[1] * cxy + g[2] * cxz;
-  const double id = 1.0 / det;
-  m.gi[0] = cxx * id; m.gi[1] = cxy * id; m.gi[2] = cxz * id;
-  m.gi[3] = cyy * id; m.gi[4] = cyz * id; m.gi[5] = czz * id;
-  m.sqrtg = sqrt(det);
+  centre_inverse(m);
 }
 
 // d_e f at the cell centre: mean over the 4 edges along e of the vertex
@@ -492,6 +482,52 @@ __device__ __forceinline__ void metric_deriv(const V& vt, uint32_t vb, uint32_t 
 #pragma unroll
     for (int q = 0; q < 3; ++q) md.db[e][q] = SHIFT ? edge_deriv(vt, VF_BETA + q, vb, se, sa, sb, inv_dx[e]) : 0.0;
   }
+}
+
+// The cell's 8 vertex values of one field, addressed like a vertex block with
+// strides 1, 2, 4.
+struct OneCorner {
+  double c[8];
+  __device__ __forceinline__ double operator()(int, uint32_t k) const { return c[k]; }
+};
+
+// Centre metric (as centre_metric) and its first derivatives (as metric_deriv)
+// from global vertices, one field at a time, so only one field's 8 vertices are
+// live at once.
+template <bool SHIFT, typename V>
+__device__ __forceinline__ void centre_metric_deriv(const V& vt, uint32_t vb, uint32_t VX, uint32_t VXY,
+                                                    const double* inv_dx, CentreMetric& m, MetricDeriv& md) {
+  const uint32_t o[8] = {0u, 1u, VX, VX + 1u, VXY, VXY + 1u, VXY + VX, VXY + VX + 1u};
+  auto field = [&](int f, double& mean, double* d) {
+    OneCorner w;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) w.c[k] = vt(f, vb + o[k]);
+    mean = 0.125 * (((w.c[0] + w.c[1]) + (w.c[2] + w.c[3])) + ((w.c[4] + w.c[5]) + (w.c[6] + w.c[7])));
+#pragma unroll
+    for (int e = 0; e < 3; ++e)
+      d[e] = edge_deriv(w, 0, 0u, 1u << e, 1u << ((e + 1) % 3), 1u << ((e + 2) % 3), inv_dx[e]);
+  };
+  double d[3];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    field(VF_GAMMA + q, m.g[q], d);
+#pragma unroll
+    for (int e = 0; e < 3; ++e) md.dg[e][q] = d[e];
+  }
+  field(VF_ALPHA, m.alpha, md.da);
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    if (SHIFT) {
+      field(VF_BETA + q, m.beta[q], d);
+#pragma unroll
+      for (int e = 0; e < 3; ++e) md.db[e][q] = d[e];
+    } else {
+      m.beta[q] = 0.0;
+#pragma unroll
+      for (int e = 0; e < 3; ++e) md.db[e][q] = 0.0;
+    }
+  }
+  centre_inverse(m);
 }
 
 // T^{mu nu} of Eq. (mhd-stress-energy-tensor) at a cell centre from the
