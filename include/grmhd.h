@@ -111,6 +111,9 @@ typedef struct {
   int32_t tile;       /* stage-kernel tile shape: -1 = library choice (16x4x3 for FP64, 16x4x4 for
                        * mixed precision), else 0 .. GRMHD_NTILE-1 */
   int32_t schedule;   /* GRMHD_SCHED_GRID | GRMHD_SCHED_QUEUE (grmhd_rk_step only) */
+  int32_t p_current;  /* grmhd_rk_step only: 0 = start with con2prim(U^n); 1 = P already holds the
+                       * primitives of U^n (as the previous grmhd_rk_step, grmhd_con2prim or the
+                       * P given to grmhd_prim2con leave it), so that con2prim is skipped */
   double eos_gamma;   /* Gamma-law EOS p = (Gamma - 1) rho eps, Gamma > 1 */
   double weno_eps;    /* WENO5-JS epsilon, e.g. 1e-6 */
   double wenoz_eps;   /* WENO5-Z epsilon, e.g. 1e-40 */
@@ -166,15 +169,18 @@ int grmhd_rhs(const grmhd_domain* dom, const grmhd_params* par, const grmhd_metr
               double* U, double* P, double* dUdt, double* max_rate, int64_t* n_fail, void* stream);
 
 /* One SSPRK step of the method of lines (Sec. II C) with fixed dt:
- * con2prim(U^n), then per stage s: U_{s+1} = U^n + c_s ((U_s - U^n) + dt L(U_s))
- * with con2prim of each new stage state, ending with P consistent with
- * U^{n+1}.  U, P are updated in place.  stage_ckpt: NULL, or device memory
- * for nstage * 8 * cell_stride doubles receiving the primitives of U^n and of
- * the stage states (as con2prim recovered them) for the adjoint.  max_rate / n_fail as above,
- * accumulated over all stages.  The con2prim of each stage state runs inside
- * the stage kernel; the primitives alternate between P and a copy in the
- * workspace and end in P.  ws: grmhd_workspace_bytes() bytes (two 8-field sets
- * and 256 bytes of tile-queue counters). */
+ * con2prim(U^n) (skipped when par->p_current = 1: P then already holds the
+ * primitives of U^n), then per stage s: U_{s+1} = U^n + c_s ((U_s - U^n) +
+ * dt L(U_s)) with con2prim of each new stage state, ending with P consistent
+ * with U^{n+1}; a sequence of steps thus recovers the primitives once per
+ * stage.  U, P are updated in place.  stage_ckpt: NULL, or device memory for
+ * nstage * 8 * cell_stride doubles receiving the primitives of U^n and of the
+ * stage states (as con2prim recovered them) for the adjoint.  max_rate /
+ * n_fail as above, accumulated over all stages.  The con2prim of each stage
+ * state runs inside the stage kernel; the primitives rotate between P and
+ * copies in the workspace and end in P.  ws: grmhd_workspace_bytes() bytes
+ * (two 8-field sets, three for SSPRK3 with p_current = 1, then 256 bytes of
+ * tile-queue counters). */
 int grmhd_rk_step(const grmhd_domain* dom, const grmhd_params* par, const grmhd_metric* met,
                   double* U, double* P, double dt, int32_t scheme, double* stage_ckpt,
                   double* max_rate, int64_t* n_fail, void* ws, size_t ws_bytes, void* stream);

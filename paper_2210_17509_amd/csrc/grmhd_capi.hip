@@ -62,6 +62,7 @@ struct StageArgs {
   // tiles still read P) and to the checkpoint ckpt
   double* Pout;
   double* ckpt;
+  double* ckpt_in;  // nullable: receives the stage's input primitives (P) of each cell
   unsigned long long* n_fail;
 };
 
@@ -296,6 +297,10 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int tg,
     double P[8], S[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) P[q] = ldg(Pb + q * a.cs, (uint32_t)c);
+    if (a.ckpt_in) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) stg(a.ckpt_in + q * a.cs + bx.cell_off, (uint32_t)c, P[q]);
+    }
     sources_T<SHIFT>(cm, md, P, a.ph.gam, S);
     if (a.mode == 0) {
 #pragma unroll
@@ -1012,6 +1017,7 @@ int check_params(const grmhd_params* p, const grmhd_domain* dom, KPhys& ph) {
   if (!(p->c2p_tol > 0.0) || p->c2p_maxit < 1 || p->c2p_maxit > 100000) return invalid("bad con2prim tolerance");
   if (p->tile < -1 || p->tile >= NTILE) return invalid("unknown tile shape");
   if (p->schedule != GRMHD_SCHED_GRID && p->schedule != GRMHD_SCHED_QUEUE) return invalid("unknown schedule");
+  if (p->p_current != 0 && p->p_current != 1) return invalid("p_current must be 0 or 1");
   if (!(p->rho_atm > 0.0) || !(p->atm_K > 0.0) || !(p->atm_gamma > 0.0) || !std::isfinite(p->rho_atm) ||
       !std::isfinite(p->atm_K) || !std::isfinite(p->atm_gamma))
     return invalid("bad atmosphere parameters");
@@ -1154,6 +1160,7 @@ StageArgs stage_args(const grmhd_domain* dom, const grmhd_params* par, const KPh
   a.persist_blocks = 0;
   a.Pout = nullptr;
   a.ckpt = nullptr;
+  a.ckpt_in = nullptr;
   a.n_fail = nullptr;
   return a;
 }
@@ -1315,12 +1322,17 @@ int grmhd_rhs(const grmhd_domain* dom, const grmhd_params* par, const grmhd_metr
   return e == hipSuccess ? GRMHD_OK : fail_hip(e, "k_stage");
 }
 
+// 8-field sets of the step workspace: the stage state W1 and one primitive
+// buffer, plus a second primitive buffer when the step starts from the caller's
+// P with an odd number of stages (so the last stage can end in P).
+static size_t step_sets(const grmhd_params* par, int32_t scheme) {
+  return (par && par->p_current == 1 && scheme == GRMHD_SSPRK3) ? 3 : 2;
+}
+
 size_t grmhd_workspace_bytes(const grmhd_domain* dom, const grmhd_params* par, int32_t scheme, int32_t for_adjoint) {
-  (void)par;
-  (void)scheme;
   if (!dom || dom->cell_stride < 1) return 0;
   const size_t field = sizeof(double) * 8 * (size_t)dom->cell_stride;
-  return for_adjoint ? 2 * field : 2 * field + QUEUE_BYTES;
+  return for_adjoint ? 2 * field : step_sets(par, scheme) * field + QUEUE_BYTES;
 }
 
 int grmhd_rk_step(const grmhd_domain* dom, const grmhd_params* par, const grmhd_metric* met, double* U, double* P,
@@ -1343,17 +1355,25 @@ int grmhd_rk_step(const grmhd_domain* dom, const grmhd_params* par, const grmhd_
   static const double c2[2] = {1.0, 0.5};
   const double* cst = scheme == GRMHD_SSPRK2 ? c2 : c3;
   const int nst = scheme == GRMHD_SSPRK2 ? 2 : 3;
-  // Workspace: the intermediate stage state W1, a second primitive buffer Pw and
-  // the tile-queue counters.  Each stage kernel recovers the primitives of the
-  // state it writes (con2prim fused into the stage), so the primitives alternate
-  // between P and Pw; the first recovery (of U^n) starts on the buffer that
-  // makes the last stage end in P.
+  // Workspace: the intermediate stage state W1, primitive buffers Pw (and Pw2)
+  // and the tile-queue counters.  Each stage kernel recovers the primitives of
+  // the state it writes (con2prim fused into the stage) into a buffer other than
+  // the one it reads.  Starting with con2prim(U^n), the primitives alternate
+  // between P and Pw, the first recovery going to the buffer that makes the
+  // last stage end in P.  Starting from the caller's P (p_current), stages
+  // before the last write Pw, Pw2, ... and the last writes P.
   const size_t fsz = 8 * (size_t)dom->cell_stride;
+  const bool pcur = par->p_current == 1;
   double* W1 = static_cast<double*>(ws);
   double* Pw = W1 + fsz;
-  double* Pcur = (nst % 2) ? Pw : P;
-  hipError_t e = launch_c2p(dom, pr, ph, met, U, P, stage_ckpt, nullptr, n_fail, s, Pcur);
-  if (e != hipSuccess) return fail_hip(e, "k_con2prim");
+  double* Pw2 = Pw + fsz;  // SSPRK3 with p_current only
+  double* Pcur = P;
+  hipError_t e = hipSuccess;
+  if (!pcur) {
+    Pcur = (nst % 2) ? Pw : P;
+    e = launch_c2p(dom, pr, ph, met, U, P, stage_ckpt, nullptr, n_fail, s, Pcur);
+    if (e != hipSuccess) return fail_hip(e, "k_con2prim");
+  }
   StageArgs a = stage_args(dom, par, ph, met, Pcur);
   a.mode = 1;
   a.dt = dt;
@@ -1361,7 +1381,7 @@ int grmhd_rk_step(const grmhd_domain* dom, const grmhd_params* par, const grmhd_
   a.n_fail = reinterpret_cast<unsigned long long*>(n_fail);
   a.Un = U;
   if (par->schedule == GRMHD_SCHED_QUEUE) {
-    a.queue = reinterpret_cast<unsigned int*>(static_cast<char*>(ws) + sizeof(double) * 2 * fsz);
+    a.queue = reinterpret_cast<unsigned int*>(static_cast<char*>(ws) + sizeof(double) * step_sets(par, scheme) * fsz);
     a.persist_blocks = persistent_blocks();
   }
   for (int st = 0; st < nst; ++st) {
@@ -1369,8 +1389,10 @@ int grmhd_rk_step(const grmhd_domain* dom, const grmhd_params* par, const grmhd_
     a.Uout = (st == nst - 1) ? U : W1;
     a.cstage = cst[st];
     a.P = Pcur;
-    a.Pout = (Pcur == P) ? Pw : P;
+    if (!pcur) a.Pout = (Pcur == P) ? Pw : P;
+    else a.Pout = (st == nst - 1) ? P : ((st % 2 == 0) ? Pw : Pw2);
     a.ckpt = (stage_ckpt && st + 1 < nst) ? stage_ckpt + (st + 1) * fsz : nullptr;
+    a.ckpt_in = (pcur && st == 0) ? stage_ckpt : nullptr;  // primitives of U^n, as given
     e = launch_stage(a, par->recon, par->precision, pr.tiles[a.tile], s);
     if (e != hipSuccess) return fail_hip(e, "k_stage");
     Pcur = a.Pout;

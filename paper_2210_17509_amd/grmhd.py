@@ -41,6 +41,7 @@ class grmhd_domain(ctypes.Structure):
 class grmhd_params(ctypes.Structure):
     _fields_ = [("recon", ctypes.c_int32), ("precision", ctypes.c_int32), ("wenoz_p", ctypes.c_int32),
                 ("c2p_maxit", ctypes.c_int32), ("tile", ctypes.c_int32), ("schedule", ctypes.c_int32),
+                ("p_current", ctypes.c_int32),
                 ("eos_gamma", ctypes.c_double), ("weno_eps", ctypes.c_double),
                 ("wenoz_eps", ctypes.c_double), ("c2p_tol", ctypes.c_double), ("rho_atm", ctypes.c_double),
                 ("atm_K", ctypes.c_double), ("atm_gamma", ctypes.c_double)]
@@ -153,10 +154,10 @@ GRMHD_SCHED_GRID, GRMHD_SCHED_QUEUE = 0, 1
 GRMHD_NTILE = 4  # stage-kernel tile shapes: 16x4x4, 8x8x4, 64x2x2, 16x4x3
 
 
-def make_params(p, tile=-1, schedule=GRMHD_SCHED_GRID):
+def make_params(p, tile=-1, schedule=GRMHD_SCHED_GRID, p_current=0):
     """grmhd_params from a paper_2210_17509_amd.inputs.Params."""
     return grmhd_params(int(p.recon), int(p.precision), int(p.wenoz_p), int(p.c2p_maxit), int(tile), int(schedule),
-                        float(p.eos_gamma),
+                        int(p_current), float(p.eos_gamma),
                         float(p.weno_eps), float(p.wenoz_eps), float(p.c2p_tol), float(p.rho_atm), float(p.atm_K),
                         float(p.atm_gamma))
 

@@ -91,7 +91,7 @@ def test_prepare_rejects_bad_boxes_without_touching_the_gpu(lib, kw, why):
 def test_entry_points_reject_unprepared_domain(lib):
     from paper_2210_17509_amd import grmhd as G
     d, keep = _domain(G)
-    par = G.grmhd_params(1, 0, 1, 100, -1, 0, 5 / 3, 1e-6, 1e-40, 1e-12, 1e-10, 100.0, 2.0)
+    par = G.grmhd_params(1, 0, 1, 100, -1, 0, 0, 5 / 3, 1e-6, 1e-40, 1e-12, 1e-10, 100.0, 2.0)
     met = G.grmhd_metric(ctypes.c_void_p(0x2000), None, ctypes.c_void_p(0x3000))
     fake = ctypes.c_void_p(0x4000)
     assert lib.grmhd_rhs(ctypes.byref(d), ctypes.byref(par), ctypes.byref(met), fake, fake, fake, None, None,
@@ -105,6 +105,11 @@ def test_entry_points_reject_unprepared_domain(lib):
 def test_workspace_size(lib):
     from paper_2210_17509_amd import grmhd as G
     d, keep = _domain(G)
-    par = G.grmhd_params(1, 0, 1, 100, -1, 0, 5 / 3, 1e-6, 1e-40, 1e-12, 1e-10, 100.0, 2.0)
+    par = G.grmhd_params(1, 0, 1, 100, -1, 0, 0, 5 / 3, 1e-6, 1e-40, 1e-12, 1e-10, 100.0, 2.0)
     assert G._lib.grmhd_workspace_bytes(ctypes.byref(d), ctypes.byref(par), 0, 0) == 2 * 8 * 8 * d.cell_stride + 256
+    assert G._lib.grmhd_workspace_bytes(ctypes.byref(d), ctypes.byref(par), 0, 1) == 2 * 8 * 8 * d.cell_stride
+    # starting from the caller's primitives, SSPRK3 needs a second primitive buffer
+    par.p_current = 1
+    assert G._lib.grmhd_workspace_bytes(ctypes.byref(d), ctypes.byref(par), 0, 0) == 3 * 8 * 8 * d.cell_stride + 256
+    assert G._lib.grmhd_workspace_bytes(ctypes.byref(d), ctypes.byref(par), 1, 0) == 2 * 8 * 8 * d.cell_stride + 256
     assert G._lib.grmhd_workspace_bytes(ctypes.byref(d), ctypes.byref(par), 0, 1) == 2 * 8 * 8 * d.cell_stride

@@ -49,11 +49,12 @@ def _interior_mask(prob):
     return np.concatenate([I.interior_mask(b).ravel() for b in prob.boxes])
 
 
-def _gpu_adjoint(prob, gout, scheme=0, steps=1):
+def _gpu_adjoint(prob, gout, scheme=0, steps=1, p_current=0):
     """GPU forward with checkpoints, then the adjoint of each step in reverse."""
     import torch
     G = H.G()
     d = H.Dev(prob)
+    d.par.p_current = p_current
     ns = 2 if scheme == 1 else 3
     cks = []
     for _ in range(steps):
@@ -87,13 +88,16 @@ def test_adjoint_matches_oracle_jvp(orc, case, scheme):
         assert abs(lhs - rhs) <= 1e-10 * ref, (case, lhs, rhs, ref)
 
 
-def test_adjoint_two_steps(orc):
+@pytest.mark.parametrize("p_current", [0, 1])
+def test_adjoint_two_steps(orc, p_current):
+    """Two steps; with p_current = 1 the forward steps start from the primitives
+    the previous step left, and checkpoint 0 is that P."""
     prob = I.config4(n=10)
     mask = _interior_mask(prob)
     rng = np.random.default_rng(4)
     U0 = orc.prim2con(prob)
     gout = rng.standard_normal(U0.shape) * mask
-    gin = _gpu_adjoint(prob, gout, 0, steps=2)
+    gin = _gpu_adjoint(prob, gout, 0, steps=2, p_current=p_current)
     dU = rng.standard_normal(U0.shape) * np.abs(U0[:, mask]).max(axis=1, keepdims=True) * mask
     _, jd, _ = orc.rk_step_jvp(prob, U0, dU, prob.P, steps=2)
     lhs, rhs = np.sum(gout * jd * mask), np.sum(gin * dU * mask)

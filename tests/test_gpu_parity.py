@@ -180,6 +180,62 @@ def test_ssprk2_and_checkpoints(orc):
         _assert_close(H.interior_fields(prob, ckg[s]), H.interior_fields(prob, Pg), TOL)
 
 
+@pytest.mark.parametrize("scheme,schedule", [(0, 0), (0, 1), (1, 0)])
+def test_rk_step_from_current_primitives(orc, scheme, schedule):
+    """p_current = 1: the step starts from the caller's P (here the primitives U
+    was built from, then those each step leaves) instead of recovering them from
+    U^n; the result matches the oracle and the default path, and checkpoint 0 is
+    the given P itself."""
+    import torch
+    g = H.G()
+    prob = _ragged()
+    steps = 3
+    d0, d1 = H.Dev(prob), H.Dev(prob)
+    d1.par.p_current = 1
+    d1.par.schedule = schedule
+    nst = 3 if scheme == 0 else 2
+    ck = torch.zeros((nst,) + tuple(d1.U.shape), dtype=torch.float64, device="cuda")
+    ws = None
+    for k in range(steps):
+        P_in = d1.P.clone()
+        last = k == steps - 1
+        ws = g.grmhd_rk_step(d1.dom, d1.par, d1.met, d1.U, d1.P, prob.dt, scheme, ck if last else None, d1.rate,
+                             d1.nfail, ws)
+    d0.step(steps, scheme=scheme)
+    Uo, Po = orc.prim2con(prob), prob.P.copy()
+    orc.rk_step(prob, Uo, Po, steps=steps, scheme=scheme)
+    U1, P1 = H.interior_fields(prob, d1.host(d1.U)), H.interior_fields(prob, d1.host(d1.P))
+    _assert_close(U1, H.interior_fields(prob, Uo), TOL, "U vs oracle")
+    _assert_close(P1, H.interior_fields(prob, Po), TOL, "P vs oracle")
+    _assert_close(U1, H.interior_fields(prob, d0.host(d0.U)), TOL, "U vs default path")
+    _assert_close(P1, H.interior_fields(prob, d0.host(d0.P)), TOL, "P vs default path")
+    assert int(d1.host(d1.nfail)[0]) == int(d0.host(d0.nfail)[0])
+    np.testing.assert_array_equal(H.interior_fields(prob, d1.host(ck)[0]), H.interior_fields(prob, d1.host(P_in)))
+    # SSPRK3 from the caller's P needs a third 8-field set of workspace
+    need = g.grmhd_workspace_bytes(d1.dom, d1.par, scheme)
+    field = 8 * 8 * d1.dom.cell_stride
+    assert need == (3 if scheme == 0 else 2) * field + 256
+    if scheme == 0:
+        small = torch.empty((2 * field + 256) // 8, dtype=torch.float64, device="cuda")
+        with pytest.raises(g.GrmhdError) as e:
+            g.grmhd_rk_step(d1.dom, d1.par, d1.met, d1.U, d1.P, prob.dt, scheme, None, None, None, small)
+        assert e.value.code == g.GRMHD_EWORKSPACE
+
+
+def test_rk_step_from_current_primitives_mixed():
+    """Mixed precision (FP32 reconstruction + HLLE) from the caller's P matches the
+    default mixed-precision path: the skipped con2prim polish moves P by an FP64
+    ulp at most, which can flip the FP32 rounding of a face value (one FP32 ulp,
+    6e-8, times dt / dx in U), hence 1e-7."""
+    prob = I.config3(n=24, steps=1)
+    d0, d1 = H.Dev(prob), H.Dev(prob)
+    d1.par.p_current = 1
+    d0.step(3)
+    d1.step(3)
+    _assert_close(H.interior_fields(prob, d1.host(d1.U)), H.interior_fields(prob, d0.host(d0.U)), 1e-7, "U")
+    _assert_close(H.interior_fields(prob, d1.host(d1.P)), H.interior_fields(prob, d0.host(d0.P)), 1e-7, "P")
+
+
 @pytest.mark.parametrize("recon", [I.RECON_MINMOD, I.RECON_WENO5, I.RECON_WENOZ])
 def test_uniform_state_bitwise(recon):
     state = [0.7, 0.3, -0.2, 0.1, 1.2, 0.5, -0.4, 0.8]
