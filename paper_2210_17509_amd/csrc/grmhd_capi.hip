@@ -297,10 +297,6 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int tg,
     double P[8], S[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) P[q] = ldg(Pb + q * a.cs, (uint32_t)c);
-    if (a.ckpt_in) {
-#pragma unroll
-      for (int q = 0; q < 8; ++q) stg(a.ckpt_in + q * a.cs + bx.cell_off, (uint32_t)c, P[q]);
-    }
     sources_T<SHIFT>(cm, md, P, a.ph.gam, S);
     if (a.mode == 0) {
 #pragma unroll
@@ -312,6 +308,10 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int tg,
         const double un = ldg(a.Un + q * a.cs + bx.cell_off, (uint32_t)c);
         const double us = ldg(a.Us + q * a.cs + bx.cell_off, (uint32_t)c);
         u[q] = un + a.cstage * ((us - un) + a.dt * (acc[q] + S[q]));
+      }
+      if (a.ckpt_in) {  // after the loads above (a store ahead of them would hold them back)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) stg(a.ckpt_in + q * a.cs + bx.cell_off, (uint32_t)c, P[q]);
       }
       if (a.Pout) {
         // con2prim of the new state while it is in registers (the same routine,
@@ -477,59 +477,55 @@ struct AdjArgs {
   KPhys ph;
 };
 
-// Face VJP: Fbar = (v_c - v_{c-1}) / dx_D, then the reverse of HLLE, of the two
-// side states and of the reconstruction, scattered onto the stencil cells of
-// the face (ghost cells map onto the interior cells they copy).
+// Reverse of one face's two reconstructions for one field: d[0..5] = the
+// adjoints (aL, aR of the left and right side values) carried back to the
+// face's stencil cells s[0..5]; a side that fell back to first order passes its
+// adjoint to its own cell.  Branch-free (a fallen-back side is differentiated
+// with a zero adjoint), so callers can add d into register arrays at constant
+// offsets.
+template <int RECON>
+__device__ __forceinline__ void recon_reverse(const double* s, double aL, double aR, bool fbL, bool fbR, double eps,
+                                              double d[6]) {
+  constexpr bool ZW = (RECON >= GRMHD_RECON_WENOZ);
+  constexpr int ZP = (RECON == RECON_WENOZ2) ? 2 : 1;
+  const double wL = fbL ? 0.0 : aL, wR = fbR ? 0.0 : aR;
+  if (RECON == GRMHD_RECON_MINMOD) {
+    double gl[3], gr[3];
+    minmod_grad(s[1], s[2], s[3], gl);
+    minmod_grad(s[4], s[3], s[2], gr);
+    d[0] = 0.0;
+    d[1] = wL * gl[0];
+    d[2] = wL * gl[1] + wR * gr[2];
+    d[3] = wL * gl[2] + wR * gr[1];
+    d[4] = wR * gr[0];
+    d[5] = 0.0;
+  } else {
+    double gl[5], gr[5];
+    weno5_vjp<ZW, ZP>(s, eps, ZP, wL, gl);
+    const double sr[5] = {s[5], s[4], s[3], s[2], s[1]};
+    weno5_vjp<ZW, ZP>(sr, eps, ZP, wR, gr);
+    d[0] = gl[0];
+    d[1] = gl[1] + gr[4];
+    d[2] = gl[2] + gr[3];
+    d[3] = gl[3] + gr[2];
+    d[4] = gl[4] + gr[1];
+    d[5] = gr[0];
+  }
+  d[2] += fbL ? aL : 0.0;
+  d[3] += fbR ? aR : 0.0;
+}
+
+// The face's forward pass (reconstruction of the two side states from the
+// stencil cells idx[0..5], the metric at the face centre, the side states and
+// HLLE) and its reverse from the flux adjoint Fb down to the adjoints qbL, qbR
+// of the two reconstructed side states; fbL, fbR: the side fell back to
+// first order (the positivity fallback).
 template <int D, int RECON, bool SHIFT>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_adj_face(AdjArgs a) {
-  const int nb = a.tab.nbox;
-  const int32_t* pre = a.tab.face_prefix + D * (nb + 1);
-  // y faces: each XCD takes a contiguous run of face blocks, so the blocks of
-  // neighbouring grid rows (overlapping stencils) share its L2 (timed: no gain
-  // for x faces, a loss for z faces)
-  const int blk = (D == 1) ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
-  const int b = find_box(pre, nb, blk);
-  const KBox& bx = a.tab.box[b];
-  const int nfx = bx.n[0] + (D == 0), nfy = bx.n[1] + (D == 1), nfz = bx.n[2] + (D == 2);
-  // Lanes past the box's last face take part (with nothing to add) in the
-  // wave-level exchange of the x faces below.
-  const int lin_raw = (blk - pre[b]) * FACE_BLOCK + threadIdx.x;
-  const bool live = lin_raw < nfx * nfy * nfz;
-  const int lin = live ? lin_raw : 0;
-  const int i = lin % nfx;
-  const int r = lin / nfx;
-  const int j = r % nfy;
-  const int k = r / nfy;
-  const int ng = bx.ng;
-  const int c = (D == 0) ? i : (D == 1 ? j : k);
-  const int nD = bx.n[D];
-  const int sD = (D == 0) ? 1 : (D == 1 ? bx.NX : bx.NXY);
-  const int base = (D == 0)   ? ((k + ng) * (bx.NXY / bx.NX) + (j + ng)) * bx.NX + ng
-                   : (D == 1) ? (k + ng) * bx.NXY + ng * bx.NX + (i + ng)
-                              : ng * bx.NXY + (j + ng) * bx.NX + (i + ng);
-  int idx[6];
-#pragma unroll
-  for (int o = 0; o < 6; ++o) {
-    const int m = c + o - 3;
-    const int mm = (m < 0) ? bx.mlo[D][(m + 3) < 0 ? 0 : m + 3] : (m >= nD ? bx.mhi[D][(m - nD) > 2 ? 2 : m - nD] : m);
-    idx[o] = base + mm * sD;
-  }
-  const double* __restrict__ Pb = a.P + bx.cell_off;
-  const double* __restrict__ Vb = a.V + bx.cell_off;
-  double* __restrict__ Gb = a.Pbar + bx.cell_off;
-  // adjoint of the face flux
-  double Fb[8];
-  bool any = false;
-  const double id = bx.inv_dx[D];
-#pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    const double vr = (c < nD) ? Vb[q * a.cs + idx[3]] : 0.0;
-    const double vl = (c >= 1) ? Vb[q * a.cs + idx[2]] : 0.0;
-    Fb[q] = live ? (vr - vl) * id : 0.0;
-    any = any || (Fb[q] != 0.0);
-  }
-  if (!__any(any)) return;  // the whole wave has nothing to propagate
+__device__ __forceinline__ void face_side_adjoints(const AdjArgs& a, const KBox& bx, const double* __restrict__ Pb,
+                                                   const int idx[6], int i, int j, int k, const double Fb[8],
+                                                   double qbL[8], double qbR[8], bool& fbL, bool& fbR) {
   // forward reconstruction values
+  const int ng = bx.ng;
   double PL[8], PR[8];
   constexpr bool ZW = (RECON >= GRMHD_RECON_WENOZ);
   constexpr int ZP = (RECON == RECON_WENOZ2) ? 2 : 1;
@@ -559,7 +555,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   SideState<double> sL, sR;
   side_v2(m, PL, sL);
   side_v2(m, PR, sR);
-  const bool fbL = !side_ok(PL, sL.v2), fbR = !side_ok(PR, sR.v2);
+  fbL = !side_ok(PL, sL.v2);
+  fbR = !side_ok(PR, sR.v2);
   if (fbL) {
 #pragma unroll
     for (int q = 0; q < 8; ++q) PL[q] = Pb[q * a.cs + idx[2]];
@@ -612,11 +609,68 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
       gUL[q] = gUR[q] = 0.0;
     }
   }
-  double qbL[8], qbR[8];
 #pragma unroll
   for (int q = 0; q < 8; ++q) qbL[q] = qbR[q] = 0.0;
   side_vjp<D>(m, PL, gam, gm1, gUL, gFL, ip == 1 ? xbp : 0.0, im == 1 ? xbm : 0.0, qbL);
   side_vjp<D>(m, PR, gam, gm1, gUR, gFR, ip == 2 ? xbp : 0.0, im == 2 ? xbm : 0.0, qbR);
+}
+
+// Face VJP: Fbar = (v_c - v_{c-1}) / dx_D, then the reverse of HLLE, of the two
+// side states and of the reconstruction, scattered onto the stencil cells of
+// the face (ghost cells map onto the interior cells they copy).
+template <int D, int RECON, bool SHIFT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_adj_face(AdjArgs a) {
+  const int nb = a.tab.nbox;
+  const int32_t* pre = a.tab.face_prefix + D * (nb + 1);
+  // y faces: each XCD takes a contiguous run of face blocks, so the blocks of
+  // neighbouring grid rows (overlapping stencils) share its L2 (timed: no gain
+  // for x faces, a loss for z faces)
+  const int blk = (D == 1) ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+  const int b = find_box(pre, nb, blk);
+  const KBox& bx = a.tab.box[b];
+  const int nfx = bx.n[0] + (D == 0), nfy = bx.n[1] + (D == 1), nfz = bx.n[2] + (D == 2);
+  // Lanes past the box's last face take part (with nothing to add) in the
+  // wave-level exchange of the x faces below.
+  const int lin_raw = (blk - pre[b]) * FACE_BLOCK + threadIdx.x;
+  const bool live = lin_raw < nfx * nfy * nfz;
+  const int lin = live ? lin_raw : 0;
+  const int i = lin % nfx;
+  const int r = lin / nfx;
+  const int j = r % nfy;
+  const int k = r / nfy;
+  const int ng = bx.ng;
+  const int c = (D == 0) ? i : (D == 1 ? j : k);
+  const int nD = bx.n[D];
+  const int sD = (D == 0) ? 1 : (D == 1 ? bx.NX : bx.NXY);
+  const int base = (D == 0)   ? ((k + ng) * (bx.NXY / bx.NX) + (j + ng)) * bx.NX + ng
+                   : (D == 1) ? (k + ng) * bx.NXY + ng * bx.NX + (i + ng)
+                              : ng * bx.NXY + (j + ng) * bx.NX + (i + ng);
+  int idx[6];
+#pragma unroll
+  for (int o = 0; o < 6; ++o) {
+    const int m = c + o - 3;
+    const int mm = (m < 0) ? bx.mlo[D][(m + 3) < 0 ? 0 : m + 3] : (m >= nD ? bx.mhi[D][(m - nD) > 2 ? 2 : m - nD] : m);
+    idx[o] = base + mm * sD;
+  }
+  const double* __restrict__ Pb = a.P + bx.cell_off;
+  const double* __restrict__ Vb = a.V + bx.cell_off;
+  double* __restrict__ Gb = a.Pbar + bx.cell_off;
+  // adjoint of the face flux
+  double Fb[8];
+  bool any = false;
+  const double id = bx.inv_dx[D];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const double vr = (c < nD) ? Vb[q * a.cs + idx[3]] : 0.0;
+    const double vl = (c >= 1) ? Vb[q * a.cs + idx[2]] : 0.0;
+    Fb[q] = live ? (vr - vl) * id : 0.0;
+    any = any || (Fb[q] != 0.0);
+  }
+  if (!__any(any)) return;  // the whole wave has nothing to propagate
+  double qbL[8], qbR[8];
+  bool fbL, fbR;
+  face_side_adjoints<D, RECON, SHIFT>(a, bx, Pb, idx, i, j, k, Fb, qbL, qbR, fbL, fbR);
+  const double eps = (RECON >= GRMHD_RECON_WENOZ) ? a.ph.wenoz_eps : a.ph.weno_eps;
   // x faces: a wave holds consecutive faces of one grid line, so the lane of the
   // face just below cell m (the cell's "owner") gathers the contributions of its
   // neighbour lanes to m and adds them with one atomic.  give[o]: stencil cell o
@@ -664,35 +718,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
       qbL[t] = qbL[t + 1];
       qbR[t] = qbR[t + 1];
     }
-    double sb[6] = {0, 0, 0, 0, 0, 0};
-    if (RECON == GRMHD_RECON_MINMOD) {
-      double g3[3];
-      if (fbL) sb[2] += aL;
-      else {
-        minmod_grad(s[1], s[2], s[3], g3);
-        sb[1] += aL * g3[0]; sb[2] += aL * g3[1]; sb[3] += aL * g3[2];
-      }
-      if (fbR) sb[3] += aR;
-      else {
-        minmod_grad(s[4], s[3], s[2], g3);
-        sb[4] += aR * g3[0]; sb[3] += aR * g3[1]; sb[2] += aR * g3[2];
-      }
-    } else {
-      double g5[5];
-      if (fbL) sb[2] += aL;
-      else {
-        weno5_vjp<ZW, ZP>(s, eps, ZP, aL, g5);
-#pragma unroll
-        for (int o = 0; o < 5; ++o) sb[o] += g5[o];
-      }
-      if (fbR) sb[3] += aR;
-      else {
-        const double sr[5] = {s[5], s[4], s[3], s[2], s[1]};
-        weno5_vjp<ZW, ZP>(sr, eps, ZP, aR, g5);
-#pragma unroll
-        for (int o = 0; o < 5; ++o) sb[5 - o] += g5[o];
-      }
-    }
+    double sb[6];
+    recon_reverse<RECON>(s, aL, aR, fbL, fbR, eps, sb);
     if (D == 0) {
       double own = 0.0;
 #pragma unroll
