@@ -56,7 +56,7 @@ struct StageArgs {
   KPhys ph;
   double* max_rate;
   unsigned int* queue;  // non-null: persistent launch over per-XCD tile queues
-  int32_t persist_blocks;
+  int32_t persist_blocks;  // compute units of the device (persistent launch)
   // mode 1 only, nullable: con2prim of each new cell state inside the stage
   // kernel, guessed from P; results to Pout (which must not alias P: other
   // tiles still read P) and to the checkpoint ckpt
@@ -1077,13 +1077,13 @@ Table make_table(const grmhd_domain* dom) {
   return t;
 }
 
-// Workgroups of a persistent launch: 2 resident 256-thread workgroups per CU
-// (the stage kernel needs ~250 VGPRs, i.e. 2 waves per SIMD).
+// Compute units of the current device (a persistent launch keeps as many
+// 256-thread workgroups per CU resident as the kernel has waves per SIMD).
 int persistent_blocks() {
   static int n = [] {
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    return 2 * cus;
+    return cus;
   }();
   return n;
 }
@@ -1100,7 +1100,8 @@ template <int RECON, typename R, bool SHIFT, int TI>
 hipError_t launch_stage_t(const StageArgs& a, int64_t blocks, hipStream_t s) {
   if (a.queue) {
     hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, s, a.queue);
-    const int64_t nb = std::min<int64_t>(blocks, a.persist_blocks);
+    // one workgroup of 4 waves per SIMD-wave slot: waves per SIMD workgroups per CU
+    const int64_t nb = std::min<int64_t>(blocks, (int64_t)a.persist_blocks * StageWaves<R, SHIFT, RECON>::value);
     hipLaunchKernelGGL((k_stage_queue<RECON, R, SHIFT, TI>), dim3((unsigned)nb), dim3(256), 0, s, a, a.queue,
                        (int)blocks);
   } else {
