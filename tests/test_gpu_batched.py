@@ -59,19 +59,24 @@ def test_batch_equals_single_boxes_bitwise():
         np.testing.assert_array_equal(ds.host(ds.P)[:, :n][:, m], Pb[:, c0:c0 + n][:, m])
 
 
-def test_batch_matches_oracle(orc):
+@pytest.mark.parametrize("p_current,steps", [(0, 1), (1, 2)])
+def test_batch_matches_oracle(orc, p_current, steps):
     prob = _small_batch(8, seed=5)
     d = H.Dev(prob)
-    d.step(1)
+    d.par.p_current = p_current
+    d.step(steps)
     Uo, Po = orc.prim2con(prob), prob.P.copy()
-    orc.rk_step(prob, Uo, Po)
+    orc.rk_step(prob, Uo, Po, steps=steps)
     for a, b in ((d.host(d.U), Uo), (d.host(d.P), Po)):
         r = H.rel_linf(H.interior_fields(prob, a), H.interior_fields(prob, b))
         assert np.all(r <= 1e-12), r
 
 
+@pytest.mark.parametrize("p_current", [0, 1])
 @pytest.mark.parametrize("tile", [0, 1, 2, 3])
-def test_queue_schedule_bitwise(tile):
+def test_queue_schedule_bitwise(tile, p_current):
+    """The persistent schedule reproduces the grid schedule bit for bit (with
+    p_current = 1 the queue counters follow a third workspace set)."""
     import torch
     G = H.G()
     for prob in (_small_batch(12, seed=7), I.config1(n=40)):
@@ -79,6 +84,7 @@ def test_queue_schedule_bitwise(tile):
         for sched in (G.GRMHD_SCHED_GRID, G.GRMHD_SCHED_QUEUE):
             d = H.Dev(prob, tile=tile)
             d.par.schedule = sched
+            d.par.p_current = p_current
             rate = torch.zeros(1, dtype=torch.float64, device="cuda")
             for _ in range(2):
                 G.grmhd_rk_step(d.dom, d.par, d.met, d.U, d.P, prob.dt, max_rate=rate)
@@ -88,8 +94,8 @@ def test_queue_schedule_bitwise(tile):
         assert outs[0][2] == outs[1][2]
 
 
-@pytest.mark.parametrize("sched", [0, 1])
-def test_graph_replay_matches_eager(sched):
+@pytest.mark.parametrize("sched,p_current", [(0, 0), (1, 0), (0, 1), (1, 1)])
+def test_graph_replay_matches_eager(sched, p_current):
     """Replays of a captured step (eager work in between) reproduce the eager step each time."""
     import torch
     from paper_2210_17509_amd.autotune import StepGraph
@@ -98,6 +104,7 @@ def test_graph_replay_matches_eager(sched):
     ge = H.Dev(prob)      # eager reference
     gg = H.Dev(prob)      # graph-driven copy
     ge.par.schedule = gg.par.schedule = sched
+    ge.par.p_current = gg.par.p_current = p_current
     graph = StepGraph(gg.dom, gg.par, gg.met, gg.U, gg.P, prob.dt, max_rate=gg.rate, n_fail=gg.nfail)
     for rep in range(3):
         G.grmhd_rk_step(ge.dom, ge.par, ge.met, ge.U, ge.P, prob.dt, max_rate=ge.rate, n_fail=ge.nfail)
