@@ -39,6 +39,14 @@ WORKLOADS = {
     "curved384-fp64": dict(kind="config3-fp64", n=384,
                            desc="static curved metric 384^3 (mixed-precision recipe and seed), WENO5, HLLE, FP64"),
     "batched400": dict(kind="config2", n=0, desc="400 uneven boxes (edges 16..64, flat/curved), WENO5, FP64"),
+    # stand-ins for the paper's setupA (static spacetime, ideal gas, RK2), its own
+    # single-GPU comparison point: the curved recipe with periodic faces, SSPRK2
+    "setupA152": dict(kind="setupA", n=152, scheme=1, paper_v100=0.44e8,
+                      desc="setupA stand-in: static curved metric 152^3, Gamma-law, WENO5, HLLE, RK2 (SSPRK2), "
+                           "periodic, FP64"),
+    "setupA240": dict(kind="setupA", n=240, scheme=1, paper_v100=0.47e8,
+                      desc="setupA stand-in: static curved metric 240^3, Gamma-law, WENO5, HLLE, RK2 (SSPRK2), "
+                           "periodic, FP64"),
 }
 
 
@@ -55,15 +63,18 @@ def make_problem(w):
         return I.config3(n=spec["n"], steps=1, precision=I.PREC_FP64)
     if spec["kind"] == "config2":
         return I.config2()
+    if spec["kind"] == "setupA":
+        return I.config1(n=spec["n"], bc=I.BC_PERIODIC)
     raise ValueError(w)
 
 
-def stage_bytes_per_cell():
+def stage_bytes_per_cell(nstage=3):
     """Algorithmic HBM bytes of one stage-kernel launch per interior cell, averaged over
-    the 3 SSPRK3 stages: P read 64, U_s read 64, U^n read 64 (stages 2, 3 only), vertex
-    metric alpha + 6 gamma_ij ~ 1 vertex per cell 56, U_{s+1} write 64, and the
-    primitives of U_{s+1} (con2prim runs inside the stage kernel) write 64."""
-    return 64 + 64 + 64 * 2.0 / 3.0 + 56 + 64 + 64
+    the stages of a step (3 for SSPRK3, 2 for SSPRK2): P read 64, U_s read 64, U^n read
+    64 (all stages but the first), vertex metric alpha + 6 gamma_ij ~ 1 vertex per cell
+    56, U_{s+1} write 64, and the primitives of U_{s+1} (con2prim runs inside the stage
+    kernel) write 64."""
+    return 64 + 64 + 64 * (nstage - 1.0) / nstage + 56 + 64 + 64
 
 
 def cpu_baseline(w, budget_s=12.0):
@@ -76,6 +87,7 @@ def cpu_baseline(w, budget_s=12.0):
     threads = min(16, os.cpu_count() or 1)
     oracle.set_threads(threads)
     kind = WORKLOADS[w]["kind"]
+    kind = "config1" if kind == "setupA" else kind
     # probe the rate on a small cube, then size the sample
     def run(n):
         p = I.config1(n=n) if kind in ("config1", "config3", "config3-fp64", "config2") else I.config0(n=n)
@@ -348,21 +360,22 @@ def run_workload(name, args):
     if args.autotune:
         from paper_2210_17509_amd.autotune import autotune
         par, _ = autotune(dom, par, met, U, P, prob.dt, reps=2)
-    ws = torch.empty(G.grmhd_workspace_bytes(dom, par) // 8, dtype=torch.float64, device="cuda")
+    scheme = WORKLOADS[name].get("scheme", G.GRMHD_SSPRK3)
+    ws = torch.empty(G.grmhd_workspace_bytes(dom, par, scheme) // 8, dtype=torch.float64, device="cuda")
     for _ in range(args.warmup):
-        G.grmhd_rk_step(dom, par, met, U, P, prob.dt, max_rate=rate, n_fail=nfail, ws=ws)
+        G.grmhd_rk_step(dom, par, met, U, P, prob.dt, scheme, max_rate=rate, n_fail=nfail, ws=ws)
     torch.cuda.synchronize()
     G.grmhd_timing_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        G.grmhd_rk_step(dom, par, met, U, P, prob.dt, max_rate=rate, n_fail=nfail, ws=ws)
+        G.grmhd_rk_step(dom, par, met, U, P, prob.dt, scheme, max_rate=rate, n_fail=nfail, ws=ws)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     times = G.grmhd_timing_read()
     G.grmhd_timing_enable(False)
     return {"prob": prob, "ncell": prob.ninterior, "wall": wall, "times": times, "nfail": int(nfail.item()),
-            "par": par, "U": U, "P": P}
+            "par": par, "U": U, "P": P, "stages": 2 if scheme == G.GRMHD_SSPRK2 else 3}
 
 
 def field_errors(prob, a, b):
@@ -426,14 +439,14 @@ def main():
     prob, ncell, wall, times, nfail, par = res["prob"], res["ncell"], res["wall"], res["times"], res["nfail"], \
         res["par"]
 
-    stages = 3
+    stages = res["stages"]
     value = ncell * stages * args.steps / wall
     st_ms, st_n = times["stage"]
     c2p_ms, c2p_n = times["con2prim"]
     avg_stage_s = st_ms / 1e3 / max(st_n, 1)
     flops_per_launch = FLOPS_PER_CELL[prob.params.recon] * ncell
     achieved = flops_per_launch / avg_stage_s / 1e12
-    hbm_gbs = stage_bytes_per_cell() * ncell / avg_stage_s / 1e9
+    hbm_gbs = stage_bytes_per_cell(stages) * ncell / avg_stage_s / 1e9
     out = {
         "metric": METRIC,
         "value": value,
@@ -457,11 +470,17 @@ def main():
                      "kernel": "k_stage", "flops_per_cell": FLOPS_PER_CELL[prob.params.recon],
                      "algorithmic_hbm_GBs": hbm_gbs, "algorithmic_hbm_frac": hbm_gbs / HBM_PEAK_GBS},
     }
+    spec = WORKLOADS[args.workload]
+    if "paper_v100" in spec:
+        # the paper's own single-GPU unit: full steps (all RK stages) of every cell per second
+        out["zone_cycles_per_s"] = ncell * args.steps / wall
+        out["paper_context"] = {"zone_cycles_per_s": spec["paper_v100"],
+                                "machine": "one Summit V100 (the paper's setupA, another machine: context only)"}
     if args.compare:
         ref = run_workload(args.compare, args)
-        out["compare"] = {"workload": WORKLOADS[args.compare]["desc"],
-                          "value": ref["ncell"] * stages * args.steps / ref["wall"],
-                          "ratio": value / (ref["ncell"] * stages * args.steps / ref["wall"])}
+        ref_value = ref["ncell"] * ref["stages"] * args.steps / ref["wall"]
+        out["compare"] = {"workload": WORKLOADS[args.compare]["desc"], "value": ref_value,
+                          "ratio": value / ref_value}
         if ref["U"].shape == res["U"].shape and ref["prob"].P.shape == prob.P.shape:
             # same grid and the same number of steps from the same initial data
             out["compare"]["U_error_vs_compare"] = field_errors(prob, res["U"], ref["U"])

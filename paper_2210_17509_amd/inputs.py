@@ -286,13 +286,14 @@ def config0(n=64, seed=SEED_BASE + 0, jump=True, recon=RECON_MINMOD, steps=1, ng
 
 
 def config1(n=256, seed=SEED_BASE + 1, recon=RECON_WENO5, steps=1, extent=4.0, ng=3,
-            precision=PREC_FP64):
+            precision=PREC_FP64, bc=BC_OUTFLOW):
     """Static curved metric on [-extent, extent]^3, Gamma = 2, polytrope-like ball,
-    outflow everywhere, WENO5 + HLLE, atmosphere 1e-10, dt = dx/4."""
+    outflow everywhere (or bc on every face), WENO5 + HLLE, atmosphere 1e-10,
+    dt = dx/4."""
     rng = np.random.default_rng(seed)
     gam = 2.0
     dx = 2.0 * extent / n
-    box = BoxSpec((n, n, n), ng, (BC_OUTFLOW,) * 6, (-extent,) * 3, (dx, dx, dx))
+    box = BoxSpec((n, n, n), ng, (bc,) * 6, (-extent,) * 3, (dx, dx, dx))
     X, Y, Z = cell_centres(box)
     f = curved_fields(rng, X, Y, Z, gam)
     par = Params(recon=recon, eos_gamma=gam, precision=precision)

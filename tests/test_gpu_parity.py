@@ -222,6 +222,19 @@ def test_rk_step_from_current_primitives(orc, scheme, schedule):
         assert e.value.code == g.GRMHD_EWORKSPACE
 
 
+def test_setupA_recipe_parity(orc):
+    """The setupA stand-in (curved recipe, periodic faces, RK2 = SSPRK2) against the
+    oracle: two steps from the current primitives."""
+    prob = I.config1(n=20, bc=I.BC_PERIODIC)
+    d = H.Dev(prob)
+    d.par.p_current = 1
+    d.step(2, scheme=1)
+    Uo, Po = orc.prim2con(prob), prob.P.copy()
+    orc.rk_step(prob, Uo, Po, steps=2, scheme=1)
+    _assert_close(H.interior_fields(prob, d.host(d.U)), H.interior_fields(prob, Uo), TOL, "U")
+    _assert_close(H.interior_fields(prob, d.host(d.P)), H.interior_fields(prob, Po), TOL, "P")
+
+
 def test_rk_step_from_current_primitives_mixed():
     """Mixed precision (FP32 reconstruction + HLLE) from the caller's P matches the
     default mixed-precision path: the skipped con2prim polish moves P by an FP64
