@@ -275,7 +275,10 @@ def rhs(prob, U, P):
 
 
 def rk_step(prob, U, P, dt=None, scheme=0, steps=1, ckpt=False):
-    """In-place RK steps (scheme 0 = SSPRK3, 1 = SSPRK2); returns (max_rate, n_fail[, ckpts])."""
+    """In-place RK steps (scheme 0 = SSPRK3, 1 = SSPRK2, 2 = classic RK4); returns
+    (max_rate, n_fail[, ckpts]).  Checkpoints are written for the SSPRK schemes only."""
+    if ckpt and scheme == 2:
+        raise ValueError("checkpoints are written for the SSPRK schemes only")
     L = lib()
     par = make_par(prob.params)
     dt = prob.dt if dt is None else dt

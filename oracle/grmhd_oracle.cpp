@@ -1087,8 +1087,37 @@ template <class T> void rhs_from_prims(const Box& bx, const Par& par, const VMet
 // SSPRK3 (Shu-Osher) in the form U_{s+1} = U^n + c_s ((U_s - U^n) + dt L(U_s)),
 // c = (1, 1/4, 2/3), which equals the textbook convex combinations and keeps a
 // state with L = 0 unchanged bit for bit.  scheme 1 = SSPRK2 (Heun), c = (1, 1/2).
+// Classic fourth-order Runge-Kutta (scheme 2): stage states U_{s+1} = U^n + a_s dt
+// L(U_s), a = (1/2, 1/2, 1), and U^{n+1} = U^n + dt (L_0 + 2 L_1 + 2 L_2 + L_3) / 6,
+// accumulated stage by stage as A_s = A_{s-1} + b_s dt L_s from A_{-1} = U^n,
+// b = (1/6, 1/3, 1/3, 1/6).  No checkpoints (the adjoint covers the SSPRK schemes).
+template <class T> long rk4_step_box(const Box& bx, const Par& par, const VMetric& vm, T* U, T* P, double dt,
+                                     double* max_rate) {
+  Geo G(bx);
+  const long N = 8 * G.ncell;
+  static const double a[3] = {0.5, 0.5, 1.0};
+  static const double b[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
+  long nfail = con2prim_box(bx, par, vm, U, P, (int32_t*)nullptr);
+  std::vector<T> Un(U, U + N), A(U, U + N), L(N);
+  for (int s = 0; s < 4; ++s) {
+    if (s > 0) nfail += con2prim_box(bx, par, vm, U, P, (int32_t*)nullptr);
+    rhs_from_prims(bx, par, vm, P, L.data(), max_rate);
+    for (int q = 0; q < 8; ++q)
+      for (long k = 0; k < G.n[2]; ++k)
+        for (long j = 0; j < G.n[1]; ++j)
+          for (long i = 0; i < G.n[0]; ++i) {
+            long x = q * G.ncell + G.c(i, j, k);
+            A[x] = A[x] + (b[s] * dt) * L[x];
+            U[x] = (s < 3) ? Un[x] + (a[s] * dt) * L[x] : A[x];
+          }
+  }
+  nfail += con2prim_box(bx, par, vm, U, P, (int32_t*)nullptr);
+  return nfail;
+}
+
 template <class T> long rk_step_box(const Box& bx, const Par& par, const VMetric& vm, T* U, T* P, double dt, int scheme,
                                     T* ckpt, double* max_rate) {
+  if (scheme == 2) return rk4_step_box(bx, par, vm, U, P, dt, max_rate);
   Geo G(bx);
   const long N = 8 * G.ncell;
   static const double c3[3] = {1.0, 0.25, 2.0 / 3.0};
