@@ -61,8 +61,11 @@ enum { GRMHD_RECON_MINMOD = 0, GRMHD_RECON_WENO5 = 1, GRMHD_RECON_WENOZ = 2 };
 /* GRMHD_MIXED: reconstruction and HLLE in FP32; con2prim, sources, the flux
  * divergence accumulation, the time update and the atmosphere stay FP64. */
 enum { GRMHD_FP64 = 0, GRMHD_MIXED = 1 };
-/* SSPRK3 (Shu-Osher) and SSPRK2 (Heun), written U_{s+1} = U^n + c_s ((U_s - U^n) + dt L(U_s)). */
-enum { GRMHD_SSPRK3 = 0, GRMHD_SSPRK2 = 1 };
+/* SSPRK3 (Shu-Osher) and SSPRK2 (Heun, the method of lines' RK2), written
+ * U_{s+1} = U^n + c_s ((U_s - U^n) + dt L(U_s)); classic RK4 with stage states
+ * U^n + a_s dt L(U_s), a = (1/2, 1/2, 1), and U^{n+1} = U^n + dt (L_0 + 2 L_1 + 2 L_2
+ * + L_3) / 6 (the paper's RK4; no stage checkpoints, no adjoint). */
+enum { GRMHD_SSPRK3 = 0, GRMHD_SSPRK2 = 1, GRMHD_RK4 = 2 };
 /* Stage-kernel tiles (cells per 256-thread workgroup): 0 = 16x4x4, 1 = 8x8x4, 2 = 64x2x2,
  * 3 = 16x4x3 (192 cells: the faces of each direction fit one pass of the workgroup). */
 #define GRMHD_NTILE 4
@@ -173,14 +176,15 @@ int grmhd_rhs(const grmhd_domain* dom, const grmhd_params* par, const grmhd_metr
  * primitives of U^n), then per stage s: U_{s+1} = U^n + c_s ((U_s - U^n) +
  * dt L(U_s)) with con2prim of each new stage state, ending with P consistent
  * with U^{n+1}; a sequence of steps thus recovers the primitives once per
- * stage.  U, P are updated in place.  stage_ckpt: NULL, or device memory for
+ * stage.  U, P are updated in place.  stage_ckpt (SSPRK schemes; NULL for RK4): NULL, or device memory for
  * nstage * 8 * cell_stride doubles receiving the primitives of U^n and of the
  * stage states (as con2prim recovered them) for the adjoint.  max_rate /
  * n_fail as above, accumulated over all stages.  The con2prim of each stage
  * state runs inside the stage kernel; the primitives rotate between P and
  * copies in the workspace and end in P.  ws: grmhd_workspace_bytes() bytes
- * (two 8-field sets, three for SSPRK3 with p_current = 1, then 256 bytes of
- * tile-queue counters). */
+ * (two 8-field sets, three for SSPRK3 with p_current = 1 and for RK4, then 256
+ * bytes of tile-queue counters).  RK4 runs con2prim as its own launch before
+ * each stage (the stage kernel then only evaluates L) and once at the end. */
 int grmhd_rk_step(const grmhd_domain* dom, const grmhd_params* par, const grmhd_metric* met,
                   double* U, double* P, double dt, int32_t scheme, double* stage_ckpt,
                   double* max_rate, int64_t* n_fail, void* ws, size_t ws_bytes, void* stream);

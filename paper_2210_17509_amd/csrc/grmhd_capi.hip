@@ -873,6 +873,29 @@ __global__ __launch_bounds__(C2P_BLOCK) __attribute__((amdgpu_waves_per_eu(SHIFT
   }
 }
 
+// Classic RK4 after stage s: A = (first ? U^n : A) + b_s dt L; then either the
+// next stage state Unext = U^n + a_s dt L or, after the last stage, U = A.
+__global__ __launch_bounds__(C2P_BLOCK) void k_rk4_combine(Table tab, double* U, const double* __restrict__ L,
+                                                            double* A, double* Unext, double adt, double bdt,
+                                                            int32_t first, int32_t last, int64_t cs) {
+  int b, c, vb;
+  if (!cell_of(tab, blockIdx.x, threadIdx.x, b, c, vb)) return;
+  const int64_t cc = tab.box[b].cell_off + c;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int64_t x = q * cs + cc;
+    const double l = L[x];
+    const double un = U[x];
+    const double acc = (first ? un : A[x]) + bdt * l;
+    if (last) {
+      U[x] = acc;
+    } else {
+      A[x] = acc;
+      Unext[x] = un + adt * l;
+    }
+  }
+}
+
 // Fill the interior cells of 8 pooled fields with a value.
 __global__ __launch_bounds__(C2P_BLOCK) void k_fill(Table tab, double* X, int64_t cs, double val) {
   int b, c, vb;
@@ -1354,6 +1377,7 @@ int grmhd_rhs(const grmhd_domain* dom, const grmhd_params* par, const grmhd_metr
 // buffer, plus a second primitive buffer when the step starts from the caller's
 // P with an odd number of stages (so the last stage can end in P).
 static size_t step_sets(const grmhd_params* par, int32_t scheme) {
+  if (scheme == GRMHD_RK4) return 3;  // stage state, L, accumulator
   return (par && par->p_current == 1 && scheme == GRMHD_SSPRK3) ? 3 : 2;
 }
 
@@ -1361,6 +1385,46 @@ size_t grmhd_workspace_bytes(const grmhd_domain* dom, const grmhd_params* par, i
   if (!dom || dom->cell_stride < 1) return 0;
   const size_t field = sizeof(double) * 8 * (size_t)dom->cell_stride;
   return for_adjoint ? 2 * field : step_sets(par, scheme) * field + QUEUE_BYTES;
+}
+
+// Classic RK4 (Sec. IV A, Sec. V setupB): per stage, con2prim of the stage state
+// into P (skipped for U^n with p_current), the stage kernel evaluating L into
+// the workspace, then k_rk4_combine; con2prim of U^{n+1} at the end.
+static int rk4_step(const grmhd_domain* dom, const Prepared& pr, const KPhys& ph, const grmhd_params* par,
+                    const grmhd_metric* met, double* U, double* P, double dt, double* max_rate, int64_t* n_fail,
+                    void* ws, hipStream_t s) {
+  static const double a4[3] = {0.5, 0.5, 1.0};
+  static const double b4[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
+  const size_t fsz = 8 * (size_t)dom->cell_stride;
+  double* W1 = static_cast<double*>(ws);  // stage state
+  double* WL = W1 + fsz;                  // L of the stage state
+  double* WA = WL + fsz;                  // accumulated step
+  const Table tab = make_table(dom);
+  StageArgs a = stage_args(dom, par, ph, met, P);
+  a.mode = 0;
+  a.max_rate = max_rate;
+  a.Uout = WL;
+  if (par->schedule == GRMHD_SCHED_QUEUE) {
+    a.queue = reinterpret_cast<unsigned int*>(static_cast<char*>(ws) + sizeof(double) * step_sets(par, GRMHD_RK4) * fsz);
+    a.persist_blocks = persistent_blocks();
+  }
+  hipError_t e = hipSuccess;
+  for (int st = 0; st < 4; ++st) {
+    double* Us = (st == 0) ? U : W1;
+    if (st > 0 || par->p_current != 1) {
+      e = launch_c2p(dom, pr, ph, met, Us, P, nullptr, nullptr, n_fail, s);
+      if (e != hipSuccess) return fail_hip(e, "k_con2prim");
+    }
+    e = launch_stage(a, par->recon, par->precision, pr.tiles[a.tile], s);
+    if (e != hipSuccess) return fail_hip(e, "k_stage");
+    hipLaunchKernelGGL(k_rk4_combine, dim3((unsigned)pr.c2p_blocks), dim3(C2P_BLOCK), 0, s, tab, U, WL, WA, W1,
+                       st < 3 ? a4[st] * dt : 0.0, b4[st] * dt, (int32_t)(st == 0), (int32_t)(st == 3),
+                       dom->cell_stride);
+    e = hipGetLastError();
+    if (e != hipSuccess) return fail_hip(e, "k_rk4_combine");
+  }
+  e = launch_c2p(dom, pr, ph, met, U, P, nullptr, nullptr, n_fail, s);
+  return e == hipSuccess ? GRMHD_OK : fail_hip(e, "k_con2prim");
 }
 
 int grmhd_rk_step(const grmhd_domain* dom, const grmhd_params* par, const grmhd_metric* met, double* U, double* P,
@@ -1372,13 +1436,16 @@ int grmhd_rk_step(const grmhd_domain* dom, const grmhd_params* par, const grmhd_
   if ((r = check_domain(dom, pr)) || (r = check_params(par, dom, ph)) || (r = check_metric(met, true))) return r;
   if (!P || !U) return invalid("null P or U");
   if (!(dt > 0.0) || !std::isfinite(dt)) return invalid("dt must be positive and finite");
-  if (scheme != GRMHD_SSPRK3 && scheme != GRMHD_SSPRK2) return invalid("unknown time integrator");
+  if (scheme != GRMHD_SSPRK3 && scheme != GRMHD_SSPRK2 && scheme != GRMHD_RK4)
+    return invalid("unknown time integrator");
+  if (scheme == GRMHD_RK4 && stage_ckpt) return invalid("stage checkpoints are written for the SSPRK schemes only");
   if (!ws) return invalid("null workspace");
   if (ws_bytes < grmhd_workspace_bytes(dom, par, scheme, 0)) {
     g_last_error = "workspace too small";
     return GRMHD_EWORKSPACE;
   }
   hipStream_t s = static_cast<hipStream_t>(stream);
+  if (scheme == GRMHD_RK4) return rk4_step(dom, pr, ph, par, met, U, P, dt, max_rate, n_fail, ws, s);
   static const double c3[3] = {1.0, 0.25, 2.0 / 3.0};
   static const double c2[2] = {1.0, 0.5};
   const double* cst = scheme == GRMHD_SSPRK2 ? c2 : c3;

@@ -24,7 +24,7 @@ if not os.path.exists(LIB_PATH):
 _lib = ctypes.CDLL(LIB_PATH)
 
 GRMHD_OK, GRMHD_EINVAL, GRMHD_EHIP, GRMHD_EWORKSPACE = 0, -1, -2, -3
-GRMHD_SSPRK3, GRMHD_SSPRK2 = 0, 1
+GRMHD_SSPRK3, GRMHD_SSPRK2, GRMHD_RK4 = 0, 1, 2
 
 
 class grmhd_box(ctypes.Structure):

@@ -222,6 +222,64 @@ def test_rk_step_from_current_primitives(orc, scheme, schedule):
         assert e.value.code == g.GRMHD_EWORKSPACE
 
 
+@pytest.mark.parametrize("case,p_current,schedule", [("ragged_weno5", 0, 0), ("config0_minmod_jump", 1, 0),
+                                                      ("shifted_metric", 1, 1)])
+def test_rk4_parity(orc, case, p_current, schedule):
+    """Classic RK4 (con2prim, L, combine per stage) against the oracle's RK4, two steps."""
+    g = H.G()
+    prob = CASES[case]()
+    d = H.Dev(prob)
+    d.par.p_current = p_current
+    d.par.schedule = schedule
+    d.step(2, scheme=g.GRMHD_RK4)
+    Uo, Po = orc.prim2con(prob), prob.P.copy()
+    rate_o, nf_o = orc.rk_step(prob, Uo, Po, steps=2, scheme=2)
+    _assert_close(H.interior_fields(prob, d.host(d.U)), H.interior_fields(prob, Uo), TOL, case + " U")
+    _assert_close(H.interior_fields(prob, d.host(d.P)), H.interior_fields(prob, Po), TOL, case + " P")
+    assert float(d.host(d.rate)[0]) == pytest.approx(rate_o, rel=1e-12)
+    assert int(d.host(d.nfail)[0]) == nf_o
+
+
+def test_rk4_refuses_checkpoints():
+    import torch
+    g = H.G()
+    prob = I.config1(n=8)
+    d = H.Dev(prob)
+    ck = torch.zeros((4,) + tuple(d.U.shape), dtype=torch.float64, device="cuda")
+    with pytest.raises(g.GrmhdError) as e:
+        g.grmhd_rk_step(d.dom, d.par, d.met, d.U, d.P, prob.dt, g.GRMHD_RK4, ck)
+    assert e.value.code == g.GRMHD_EINVAL
+
+
+def test_balsara1_rk4_cfl08_gpu():
+    """Sec. IV A on the GPU with the paper's shock-tube settings: Balsara 1, 1600
+    cells, minmod, HLLE, classic RK4 at dt/dx = 0.8; the peak Lorentz factor at
+    t = 0.4 is the printed W ~ 1.458 (within 0.01) and no cell fails con2prim."""
+    import json
+    g = H.G()
+    with open(os.path.join(os.path.dirname(__file__), "golden", "balsara_table1.json")) as f:
+        tab = json.load(f)
+    t = tab["tests"]["balsara1"]
+    L, R = t["left"], t["right"]
+    N = 1600
+
+    def fields(X, Y, Z):
+        left = X < 0
+        rho, eps, vx, vy, vz, bx, by, bz = [np.where(left, l, r) for l, r in zip(L, R)]
+        return [rho, vx, vy, vz, eps, bx, by, bz]
+
+    bc = (I.BC_OUTFLOW, I.BC_OUTFLOW) + (I.BC_PERIODIC,) * 4
+    prob = T.build((N, 1, 1), fields, bc=bc, x0=(-0.5, 0, 0), dx=(1.0 / N, 1.0, 1.0),
+                   params=I.Params(recon=I.RECON_MINMOD, eos_gamma=t["gamma"]), dt=0.8 / N)
+    d = H.Dev(prob)
+    d.par.p_current = 1
+    d.step(int(round(t["t_ref"] / prob.dt)), scheme=g.GRMHD_RK4)
+    Pi = T.interior(prob, d.host(d.P))[:, 0, 0, :]
+    W = 1.0 / np.sqrt(1.0 - (Pi[1] ** 2 + Pi[2] ** 2 + Pi[3] ** 2))
+    assert int(d.host(d.nfail)[0]) == 0
+    assert abs(W.max() - tab["printed_values"]["balsara1_max_W_at_t_ref"]["value"]) < 0.01, W.max()
+
+
 def test_setupA_recipe_parity(orc):
     """The setupA stand-in (curved recipe, periodic faces, RK2 = SSPRK2) against the
     oracle: two steps from the current primitives."""
