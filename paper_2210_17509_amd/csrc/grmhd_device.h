@@ -209,7 +209,9 @@ __device__ __forceinline__ void side_v2(const FaceMetric<RM>& m, const R* P, Sid
 template <typename R> __device__ __forceinline__ bool side_ok(const R* P, R v2) {
   bool fin = true;
 #pragma unroll
-  for (int q = 0; q < 8; ++q) fin = fin && (P[q] - P[q] == R(0));  // false for inf and NaN
+  // an exact class test: "x - x == 0" is not one under FMA contraction, which
+  // can turn it into fma(a, b, -x) = the rounding error of a product x = a b
+  for (int q = 0; q < 8; ++q) fin = fin && __builtin_isfinite(P[q]);
   return fin && (P[0] > R(0)) && (P[4] > R(0)) && (v2 < R(1));
 }
 
@@ -701,7 +703,8 @@ struct C2PIn {
   double S2, B2, SB;
 };
 
-__device__ __forceinline__ bool dfinite(double x) { return x - x == 0.0; }
+// Finite (not inf, not NaN), by the exponent class; contraction-proof (see side_ok).
+__device__ __forceinline__ bool dfinite(double x) { return __builtin_isfinite(x); }
 
 // 3D Newton-Raphson in (W, z = rho h W^2, T = p / rho) (Sec. II C).  With
 // B.v = S.B / z and S_j = (z + B^2) v_j - (B.v) B_j the three equations are

@@ -280,6 +280,40 @@ def test_balsara1_rk4_cfl08_gpu():
     assert abs(W.max() - tab["printed_values"]["balsara1_max_W_at_t_ref"]["value"]) < 0.01, W.max()
 
 
+@pytest.mark.parametrize("name", ["balsara1", "balsara2", "balsara3", "balsara4", "balsara5"])
+def test_balsara_tubes_rk4_parity(orc, name):
+    """The five Table I shock tubes (Sec. IV A) on 200 cells, minmod, HLLE, classic
+    RK4 at dt/dx = 0.8 for 25 steps: the GPU against the oracle.  Strong shocks,
+    p up to 1000 and the W = 22.4 streams of test 4; con2prim failure counts
+    bit-exact, fields within 1e-12 (1e-10 for test 4: the inversion is
+    conditioned like W^2)."""
+    import json
+    g = H.G()
+    with open(os.path.join(os.path.dirname(__file__), "golden", "balsara_table1.json")) as f:
+        tab = json.load(f)
+    t = tab["tests"][name]
+    L, R = t["left"], t["right"]
+    N = 200
+
+    def fields(X, Y, Z):
+        left = X < 0
+        rho, eps, vx, vy, vz, bx, by, bz = [np.where(left, l, r) for l, r in zip(L, R)]
+        return [rho, vx, vy, vz, eps, bx, by, bz]
+
+    bc = (I.BC_OUTFLOW, I.BC_OUTFLOW) + (I.BC_PERIODIC,) * 4
+    prob = T.build((N, 1, 1), fields, bc=bc, x0=(-0.5, 0, 0), dx=(1.0 / N, 1.0, 1.0),
+                   params=I.Params(recon=I.RECON_MINMOD, eos_gamma=t["gamma"]), dt=0.8 / N)
+    d = H.Dev(prob)
+    d.par.p_current = 1
+    d.step(25, scheme=g.GRMHD_RK4)
+    Uo, Po = orc.prim2con(prob), prob.P.copy()
+    _, nf_o = orc.rk_step(prob, Uo, Po, steps=25, scheme=2)
+    tol = 1e-10 if name == "balsara4" else TOL
+    _assert_close(H.interior_fields(prob, d.host(d.U)), H.interior_fields(prob, Uo), tol, name + " U")
+    _assert_close(H.interior_fields(prob, d.host(d.P)), H.interior_fields(prob, Po), tol, name + " P")
+    assert int(d.host(d.nfail)[0]) == nf_o
+
+
 def test_setupA_recipe_parity(orc):
     """The setupA stand-in (curved recipe, periodic faces, RK2 = SSPRK2) against the
     oracle: two steps from the current primitives."""
