@@ -134,6 +134,32 @@ def test_con2prim_failures_and_atmosphere(orc):
     _assert_close(H.interior_fields(prob, d.host(d.U)), H.interior_fields(prob, Uo), TOL)
 
 
+def test_con2prim_newman_hamlin_recovery(orc):
+    """A strongly magnetised state behind a Balsara 2 shock (B^2 = 40, S^2 = 890)
+    seeded with the pre-shock primitives: the 3D Newton diverges, the
+    Newman-Hamlin fallback recovers it (status 5) with the oracle's primitives.
+    Regression: a finiteness test written x - x == 0 was contracted into
+    fma(a, b, -x) and rejected the fallback's first (finite) pressure."""
+    import torch
+    prob = T.build((4, 4, 4), T.uniform_fields([1.0, 0.0, 0.0, 0.0, 1.5, 5.0, 0.7, 0.7]),
+                   params=I.Params(recon=I.RECON_MINMOD, eos_gamma=5.0 / 3.0))
+    U = orc.prim2con(prob)
+    Uv = prob.box_view(U, 0)
+    g = prob.boxes[0].ng
+    Uv[:, g + 1, g + 2, g + 1] = [1.0, 25.804, -10.6, -10.6, 45.09551569773622, 5.0, 2.753021556739678,
+                                  2.753021556739678]
+    Po, Uo = prob.P.copy(), U.copy()
+    st_o, _ = orc.con2prim(prob, Uo, Po)
+    d = H.Dev(prob)
+    d.U.copy_(torch.as_tensor(U))
+    status = torch.zeros(prob.cell_stride, dtype=torch.int32, device="cuda")
+    H.G().grmhd_con2prim(d.dom, d.par, d.met, d.U, d.P, status, d.nfail)
+    m = I.interior_mask(prob.boxes[0]).ravel()
+    np.testing.assert_array_equal(d.host(status)[m], st_o[m])
+    assert 5 in set(st_o[m].tolist())
+    _assert_close(H.interior_fields(prob, d.host(d.P)), H.interior_fields(prob, Po), TOL)
+
+
 @pytest.mark.parametrize("tile", [0, 1, 2, 3])
 @pytest.mark.parametrize("case", sorted(CASES))
 def test_rhs_parity(orc, case, tile):
