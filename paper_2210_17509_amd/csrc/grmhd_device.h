@@ -343,16 +343,14 @@ __device__ __forceinline__ R weno5(R a, R b, R c, R d, R e, R eps, int zp) {
   const R b2 = R(13.0 / 12.0) * rsq(c - R(2) * d + e) + R(0.25) * rsq(R(3) * c - R(4) * d + e);
   R w0, w1, w2;
   weno5_weights<ZW>(b0, b1, b2, eps, zp, w0, w1, w2);
-  // An IEEE division: the refined hardware reciprocal used elsewhere reproduces this
-  // quotient in isolation, but gave wrong stage-kernel results in this position.
-  return (w0 * q0 + w1 * q1 + w2 * q2) / (R(6) * (w0 + w1 + w2));
+  return (w0 * q0 + w1 * q1 + w2 * q2) * rcp_r(R(6) * (w0 + w1 + w2));
 }
 
 // Both WENO5 values at the face between cells s[2] and s[3] of the six-cell
 // stencil s[0..5]: PL from (s0, .., s4), PR from the mirrored (s5, .., s1).
 // The two sides share two of their three candidate values (q1 of one side is q2
 // of the other) and two of their three second differences (those over cells
-// 1..3 and 2..4).  In FP64 one IEEE division serves both normalisations while
+// 1..3 and 2..4).  In FP64 one reciprocal serves both normalisations while
 // the product of the two denominators stays well inside the exponent range
 // (not for WENO-Z with p = 2, whose denominators can reach 1e-240).
 template <bool ZW, int ZPC = 0, typename R>
@@ -378,7 +376,7 @@ __device__ __forceinline__ void weno5_lr(const R* s, R eps, int zp, R& PL, R& PR
   const R nR = r0 * qd + r1 * qc + r2 * qb, dR = R(6) * (r0 + r1 + r2);
   const R prod = dL * dR;
   if (sizeof(R) == 8 && !(ZW && zp == 2) && prod > R(1e-300) && prod < R(1e300)) {
-    const R inv = R(1) / prod;
+    const R inv = rcp_r(prod);
     PL = nL * (dR * inv);
     PR = nR * (dL * inv);
   } else {
