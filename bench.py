@@ -202,12 +202,29 @@ SQ_PASSES = (
     "SQ_ACTIVE_INST_ANY",
     "SQ_INSTS_VMEM_RD SQ_INST_LEVEL_VMEM SQ_INSTS_LDS SQ_LDS_BANK_CONFLICT SQ_INSTS_SALU SQ_INSTS_VALU_CVT "
     "SQ_INSTS_VALU_TRANS_F32 SQ_INSTS_VALU_TRANS_F64",
+    # optional third pass: the FP64 instruction mix
+    "SQ_WAVES SQ_INSTS_VALU_ADD_F64 SQ_INSTS_VALU_MUL_F64 SQ_INSTS_VALU_FMA_F64 SQ_INSTS_VALU_TRANS_F64",
 )
+
+
+def _stats_avg_ms(name_part):
+    """Mean duration of a kernel in the committed kernel-statistics summary, or None."""
+    path = os.path.join(ROOT, "profiles", "kernels_curved256_stats.txt")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        for line in fh:
+            f = line.split()
+            if len(f) > 5 and name_part in line and f[0].isdigit():
+                return float(f[1])
+    return None
 
 
 def sq_summary(args):
     """Write profiles/k_stage_<workload>_sq.txt from the two rocprofv3 --pmc runs of SQ_PASSES."""
     dirs = args.sq_summary
+    if len(dirs) not in (2, 3):
+        raise SystemExit("--sq-summary takes the two (or three) SQ pass folders")
     means, kernel, ndisp = {}, None, None
     for d, names in zip(dirs, SQ_PASSES):
         for c in names.split():
@@ -223,12 +240,27 @@ def sq_summary(args):
              "quad-cycles, summed over SEs)",
              "# Commands (repository root, one MI355X):",
              f"#   rocprofv3 --pmc {SQ_PASSES[0]} " + run.format("S1"),
-             f"#   rocprofv3 --pmc {SQ_PASSES[1]} " + run.format("S2"),
-             f"#   python bench.py --workload {args.workload} --sq-summary S1 S2",
+             f"#   rocprofv3 --pmc {SQ_PASSES[1]} " + run.format("S2")]
+    if len(dirs) == 3:
+        lines.append(f"#   rocprofv3 --pmc {SQ_PASSES[2]} " + run.format("S3"))
+    lines += [f"#   python bench.py --workload {args.workload} --sq-summary S1 S2" + (" S3" if len(dirs) == 3 else ""),
              f"kernel_source_sha256: {kernel_source_hash()}",
              f"kernel: {kernel}"]
     for c in sorted(means):
         lines.append(f"{c}: {means[c]:.4e}  ({means[c] / waves:.1f} per wave)")
+    if "SQ_INSTS_VALU_FMA_F64" in means:
+        # each FP64 VALU instruction of a wave covers 64 lanes (inactive ones included)
+        lane_flops = 64.0 * (means["SQ_INSTS_VALU_ADD_F64"] + means["SQ_INSTS_VALU_MUL_F64"] +
+                             means["SQ_INSTS_VALU_TRANS_F64"] + 2.0 * means["SQ_INSTS_VALU_FMA_F64"])
+        ncell = WORKLOADS[args.workload]["n"] ** 3
+        alg = FLOPS_PER_CELL[1] * ncell
+        lines.append(f"issued FP64 lane-flops per launch (64 x (ADD + MUL + TRANS + 2 FMA)): {lane_flops:.4e}"
+                     f" = {lane_flops / alg:.2f} x the counted right-hand side ({alg:.4e}; con2prim and"
+                     " masked lanes account for the rest)")
+        ms = _stats_avg_ms("k_stage<1, double, false, 3>")
+        if ms:
+            lines.append(f"issued FP64 rate at the kernel-trace mean {ms:.4f} ms: {lane_flops / ms / 1e9:.1f} TFLOP/s"
+                         f" = {lane_flops / ms / 1e9 / FP64_VECTOR_PEAK_TFLOPS:.3f} of the FP64 vector peak")
     lines.append("waiting share of wave cycles (SQ_WAIT_ANY / SQ_WAVE_CYCLES): "
                  f"{means['SQ_WAIT_ANY'] / means['SQ_WAVE_CYCLES']:.3f}")
     path = os.path.join(ROOT, "profiles", f"k_stage_{args.workload}_sq.txt")
@@ -410,8 +442,9 @@ def main():
     ap.add_argument("--stats-summary", nargs=2, metavar=("STATS_DIR", "COMMAND"),
                     help="write profiles/kernels_<workload>_stats.txt (with --adjoint: kernels_adjoint128_stats.txt) "
                          "from a rocprofv3 --stats folder")
-    ap.add_argument("--sq-summary", nargs=2, metavar=("SQ_PASS1_DIR", "SQ_PASS2_DIR"),
-                    help="write profiles/k_stage_<workload>_sq.txt from the two rocprofv3 --pmc SQ passes")
+    ap.add_argument("--sq-summary", nargs="+", metavar="SQ_PASS_DIR",
+                    help="write profiles/k_stage_<workload>_sq.txt from the two (or three, with the FP64 "
+                         "instruction mix) rocprofv3 --pmc SQ passes")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
