@@ -44,6 +44,9 @@ WORKLOADS = {
     "setupA152": dict(kind="setupA", n=152, scheme=1, paper_v100=0.44e8,
                       desc="setupA stand-in: static curved metric 152^3, Gamma-law, WENO5, HLLE, RK2 (SSPRK2), "
                            "periodic, FP64"),
+    # classic RK4 (con2prim as its own launch per stage, L, combine)
+    "curved256-rk4": dict(kind="config1", n=256, scheme=2,
+                          desc="static curved metric 256^3, WENO5, HLLE, FP64, classic RK4"),
     "setupA240": dict(kind="setupA", n=240, scheme=1, paper_v100=0.47e8,
                       desc="setupA stand-in: static curved metric 240^3, Gamma-law, WENO5, HLLE, RK2 (SSPRK2), "
                            "periodic, FP64"),
@@ -407,7 +410,7 @@ def run_workload(name, args):
     times = G.grmhd_timing_read()
     G.grmhd_timing_enable(False)
     return {"prob": prob, "ncell": prob.ninterior, "wall": wall, "times": times, "nfail": int(nfail.item()),
-            "par": par, "U": U, "P": P, "stages": 2 if scheme == G.GRMHD_SSPRK2 else 3}
+            "par": par, "U": U, "P": P, "stages": {G.GRMHD_SSPRK3: 3, G.GRMHD_SSPRK2: 2, G.GRMHD_RK4: 4}[scheme]}
 
 
 def field_errors(prob, a, b):
