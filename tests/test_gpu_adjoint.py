@@ -37,8 +37,18 @@ def _shifted():
     return T.build((8, 9, 7), T.smooth_fields(13, 5.0 / 3.0), met, params=I.Params(recon=I.RECON_WENOZ))
 
 
+def _thin():
+    """A 2 x 5 x 1 box, outflow in x and z, periodic in y: the stencils of the
+    short lines fold onto one or two interior cells."""
+    met = T.conformal_metric(lambda X, Y, Z: 1.0 + 0.05 * np.sin(2 * np.pi * Y), alpha_fn=lambda X, Y, Z: 0.95 + 0 * X)
+    bc = (I.BC_OUTFLOW, I.BC_OUTFLOW, I.BC_PERIODIC, I.BC_PERIODIC, I.BC_OUTFLOW, I.BC_OUTFLOW)
+    return T.build((2, 5, 1), T.smooth_fields(14, 2.0), met, bc=bc, dx=(0.2, 0.2, 0.2),
+                   params=I.Params(recon=I.RECON_WENOZ, eos_gamma=2.0))
+
+
 CASES = {
     "wenoz_flat": lambda: I.config4(n=10),
+    "wenoz_thin_box": _thin,
     "weno5_curved": _smooth_curved,
     "minmod_flat_jump": lambda: I.config0(n=10),
     "wenoz_shifted": _shifted,

@@ -72,6 +72,23 @@ def test_batch_matches_oracle(orc, p_current, steps):
         assert np.all(r <= 1e-12), r
 
 
+@pytest.mark.parametrize("recon", [I.RECON_MINMOD, I.RECON_WENO5, I.RECON_WENOZ])
+def test_thin_boxes_match_oracle(orc, recon):
+    """Boxes of 1 to 5 cells a side, fewer than the reconstruction stencil
+    reaches: the outflow ghost map sends several stencil cells of a face to the
+    same interior cell, and most tiles are mostly empty."""
+    prob = I.config2(nbox=12, seed=11, edges=(1, 2, 3, 5), recon=recon)
+    assert min(min(b.n) for b in prob.boxes) == 1
+    d = H.Dev(prob)
+    d.step(2)
+    Uo, Po = orc.prim2con(prob), prob.P.copy()
+    _, nfail = orc.rk_step(prob, Uo, Po, steps=2)
+    assert nfail == 0
+    for a, b in ((d.host(d.U), Uo), (d.host(d.P), Po)):
+        r = H.rel_linf(H.interior_fields(prob, a), H.interior_fields(prob, b))
+        assert np.all(r <= 1e-12), r
+
+
 @pytest.mark.parametrize("p_current", [0, 1])
 @pytest.mark.parametrize("tile", [0, 1, 2, 3])
 def test_queue_schedule_bitwise(tile, p_current):
