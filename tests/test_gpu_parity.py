@@ -388,6 +388,24 @@ def test_conservation_periodic():
         assert abs(dd[q].sum()) <= 1e-13 * np.abs(dd[q]).sum()
 
 
+@pytest.mark.parametrize("n", [(1, 2, 3), (2, 1, 5)])
+@pytest.mark.parametrize("recon", [I.RECON_MINMOD, I.RECON_WENO5, I.RECON_WENOZ])
+def test_periodic_box_narrower_than_ghosts(orc, n, recon):
+    """Periodic box with 1 or 2 cells along an axis, fewer than its 3 ghost
+    layers: the periodic ghost map wraps more than once."""
+    met = T.conformal_metric(lambda X, Y, Z: 1.0 + 0.05 * np.sin(2 * np.pi * Z),
+                             alpha_fn=lambda X, Y, Z: 0.95 + 0 * X)
+    prob = T.build(n, T.smooth_fields(15, 5.0 / 3.0), met, dx=(0.2, 0.2, 0.2), params=I.Params(recon=recon))
+    d = H.Dev(prob)
+    d.step(2)
+    Uo, Po = orc.prim2con(prob), prob.P.copy()
+    _, nfail = orc.rk_step(prob, Uo, Po, steps=2)
+    assert nfail == 0
+    for a, b in ((d.host(d.U), Uo), (d.host(d.P), Po)):
+        r = H.rel_linf(H.interior_fields(prob, a), H.interior_fields(prob, b))
+        assert np.all(r <= 1e-12), r
+
+
 def test_config0_full_size(orc):
     """64^3 minmod with the jump: every interior cell against the oracle."""
     prob = I.config0()
