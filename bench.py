@@ -108,7 +108,7 @@ def cpu_baseline(w, budget_s=12.0):
 
 
 KERNEL_SOURCES = ("paper_2210_17509_amd/csrc/grmhd_capi.hip", "paper_2210_17509_amd/csrc/grmhd_device.h",
-                  "include/grmhd.h")
+                  "paper_2210_17509_amd/csrc/grmhd_adjoint.h", "include/grmhd.h")
 
 
 def kernel_source_hash():

@@ -84,7 +84,9 @@ enum {
 
 /* (host) One box of the pooled grid. */
 typedef struct {
-  int32_t n[3];      /* interior cells per axis, >= 1 */
+  int32_t n[3];      /* interior cells per axis, >= 1; a box holds fewer than 2^29
+                      * cells and vertices, ghosts included (at most 805^3 interior
+                      * cells with ng = 3): larger grids are split into boxes */
   int32_t ng;        /* ghost layers */
   int32_t bc[6];     /* x-lo, x-hi, y-lo, y-hi, z-lo, z-hi: GRMHD_BC_* */
   double x0[3];      /* coordinates of the interior's lower corner (a vertex) */

@@ -80,6 +80,11 @@ def lib():
         L.orc_point_sources.argtypes = [_D, ctypes.c_double, _D, _D, _D, _D, _D, ctypes.c_double, ctypes.c_int,
                                         _D]
         L.orc_count_ops.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_long)]
+        L.orc_point_nh_map.argtypes = [_D, _D, pp, ctypes.c_double, _D]
+        L.orc_point_nh_map.restype = ctypes.c_int
+        L.orc_point_nh_solve.argtypes = [_D, _D, pp, ctypes.c_double, _D]
+        L.orc_point_nh_solve.restype = ctypes.c_int
+        L.orc_fill_ghosts.argtypes = [pb, _D]
         _lib = L
     return _lib
 
@@ -171,6 +176,29 @@ def point_c2p(U, guess, params, g=(1, 0, 0, 1, 0, 1)):
     U, P, g = _arr(U, 8).copy(), _arr(guess, 8).copy(), _arr(g, 6)
     st = lib().orc_point_c2p(_p(U), _p(P), _p(g), ctypes.byref(make_par(params)))
     return P, U, st
+
+
+def point_nh_map(U, p, params, g=(1, 0, 0, 1, 0, 1)):
+    """One Newman-Hamlin map p -> p' of the conserved state U: (ok, p', W, z)."""
+    U, g = _arr(U, 8), _arr(g, 6)
+    out = np.zeros(3)
+    ok = lib().orc_point_nh_map(_p(U), _p(g), ctypes.byref(make_par(params)), float(p), _p(out))
+    return bool(ok), out[0], out[1], out[2]
+
+
+def point_nh_solve(U, p0, params, g=(1, 0, 0, 1, 0, 1)):
+    """The Newman-Hamlin pressure iteration alone from p0: (ok, p, W, z, T)."""
+    U, g = _arr(U, 8), _arr(g, 6)
+    out = np.zeros(4)
+    ok = lib().orc_point_nh_solve(_p(U), _p(g), ctypes.byref(make_par(params)), float(p0), _p(out))
+    return bool(ok), out[0], out[1], out[2], out[3]
+
+
+def fill_ghosts(spec, P):
+    """Boundary fill of one box's (8, ncell) primitive array (returns a filled copy)."""
+    Pb = np.ascontiguousarray(np.array(P, dtype=np.float64))
+    lib().orc_fill_ghosts(ctypes.byref(make_box(spec)), _p(Pb))
+    return Pb
 
 
 def point_hlle(PL, PR, gam, d, alpha=1.0, beta=None, g=(1, 0, 0, 1, 0, 1)):

@@ -761,6 +761,24 @@ template <class T> int recover(const PMetric<T>& m, const C2PIn<T>& c, const Par
   return C2P_OK;
 }
 
+// Undensitize U (divide by sqrt(gamma)) and form S^2 = gamma^ij S_i S_j,
+// B^2 = gamma_ij B^i B^j and S.B = S_i B^i.
+template <class T> void c2p_inputs(const PMetric<T>& m, const T* U, C2PIn<T>& c) {
+  c.Dt = U[0] / m.sqrtg;
+  for (int j = 0; j < 3; ++j) c.St[j] = U[1 + j] / m.sqrtg;
+  c.taut = U[4] / m.sqrtg;
+  for (int k = 0; k < 3; ++k) c.B[k] = U[5 + k] / m.sqrtg;
+  c.S2 = T(0.0);
+  c.B2 = T(0.0);
+  c.SB = T(0.0);
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      c.S2 = c.S2 + m.ginv[sym(i, j)] * c.St[i] * c.St[j];
+      c.B2 = c.B2 + m.g[sym(i, j)] * c.B[i] * c.B[j];
+    }
+  for (int i = 0; i < 3; ++i) c.SB = c.SB + c.St[i] * c.B[i];
+}
+
 template <class T> int con2prim_point(const PMetric<T>& m, const Par& par, const AtmData& atm, T* U, T* P) {
   for (int q = 0; q < 8; ++q)
     if (!finite(U[q])) {
@@ -771,23 +789,11 @@ template <class T> int con2prim_point(const PMetric<T>& m, const Par& par, const
   const double gam = par.gam;
   const double gf = gam / (gam - 1.0);
   C2PIn<T> c;
-  c.Dt = U[0] / m.sqrtg;
-  for (int j = 0; j < 3; ++j) c.St[j] = U[1 + j] / m.sqrtg;
-  c.taut = U[4] / m.sqrtg;
-  for (int k = 0; k < 3; ++k) c.B[k] = U[5 + k] / m.sqrtg;
+  c2p_inputs(m, U, c);
   if (c.Dt < atm.rho) {
     atmosphere(m, par, atm, U, P);
     return C2P_FLOOR;
   }
-  c.S2 = T(0.0);
-  c.B2 = T(0.0);
-  c.SB = T(0.0);
-  for (int i = 0; i < 3; ++i)
-    for (int j = 0; j < 3; ++j) {
-      c.S2 = c.S2 + m.ginv[sym(i, j)] * c.St[i] * c.St[j];
-      c.B2 = c.B2 + m.g[sym(i, j)] * c.B[i] * c.B[j];
-    }
-  for (int i = 0; i < 3; ++i) c.SB = c.SB + c.St[i] * c.B[i];
 
   // initial guess from the supplied primitives
   T W, z, Tt, p0;
@@ -1278,6 +1284,43 @@ int orc_point_c2p(double* U, double* P, const double* g, const Par* par) {
   PMetric<double> m = point_metric(1.0, zero, g);
   AtmData atm = atm_of(*par);
   return con2prim_point(m, *par, atm, U, P);
+}
+
+// One Newman-Hamlin map p -> p' for the conserved state U (spatial metric g):
+// out = (p', W, z).  Returns 0 when the map has no physical image.
+int orc_point_nh_map(const double* U, const double* g, const Par* par, double p, double* out) {
+  const double zero[3] = {0, 0, 0};
+  PMetric<double> m = point_metric(1.0, zero, g);
+  C2PIn<double> c;
+  c2p_inputs(m, U, c);
+  double pn = 0, W = 0, z = 0;
+  const bool ok = nh_map(c, par->gam, p, pn, W, z);
+  out[0] = pn;
+  out[1] = W;
+  out[2] = z;
+  return ok ? 1 : 0;
+}
+
+// The Newman-Hamlin pressure iteration alone (no Newton polish) from p0:
+// out = (p, W, z, T).  Returns 1 on convergence.
+int orc_point_nh_solve(const double* U, const double* g, const Par* par, double p0, double* out) {
+  const double zero[3] = {0, 0, 0};
+  PMetric<double> m = point_metric(1.0, zero, g);
+  C2PIn<double> c;
+  c2p_inputs(m, U, c);
+  double W = 0, z = 0, Tt = 0;
+  const bool ok = newman_hamlin(c, *par, p0, W, z, Tt);
+  out[0] = ok ? c.Dt * Tt / W : 0.0;
+  out[1] = W;
+  out[2] = z;
+  out[3] = Tt;
+  return ok ? 1 : 0;
+}
+
+// Boundary fill of the 8 primitive fields of one box (ghost cells only).
+void orc_fill_ghosts(const Box* bx, double* P) {
+  Geo G(*bx);
+  fill_ghosts(*bx, G, P);
 }
 
 void orc_point_hlle(const double* PL, const double* PR, double alpha, const double* beta, const double* g, double gam,

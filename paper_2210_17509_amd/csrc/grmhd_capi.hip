@@ -1018,7 +1018,10 @@ int check_box(const grmhd_box& b, int64_t cs, int64_t vs) {
   if (b.ng < 2 || b.ng > 16) return invalid("ghost layers must be in [2, 16]");
   const int64_t NX = b.n[0] + 2 * b.ng, NY = b.n[1] + 2 * b.ng, NZ = b.n[2] + 2 * b.ng;
   const int64_t nc = NX * NY * NZ, nv = (NX + 1) * (NY + 1) * (NZ + 1);
-  if (nv >= (int64_t(1) << 31)) return invalid("box too large for 32-bit indexing");
+  // The stage kernel addresses a box's cells and vertices as base + 32-bit byte
+  // offset (element index << 3), so every element index must stay below 2^29.
+  if (nc >= (int64_t(1) << 29) || nv >= (int64_t(1) << 29))
+    return invalid("box too large: cells or vertices with ghosts reach 2^29 (32-bit byte offsets)");
   if (b.cell_off < 0 || b.cell_off + nc > cs) return invalid("box cells outside the cell stride");
   if (b.vert_off < 0 || b.vert_off + nv > vs) return invalid("box vertices outside the vertex stride");
   return GRMHD_OK;

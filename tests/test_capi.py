@@ -79,6 +79,10 @@ def _domain(G, n=(8, 8, 8), ng=3, bc=(0,) * 6, cell_stride=None, vert_stride=Non
     (dict(bc=(7, 7, 0, 0, 0, 0)), "unknown boundary"),
     (dict(cell_stride=10), "outside the cell stride"),
     (dict(dx=-1.0), "dx"),
+    # 812^3 storage cells and 813^3 vertices: element indices past 2^29 would
+    # wrap the stage kernel's 32-bit byte offsets
+    (dict(n=(806, 806, 806)), "2^29"),
+    (dict(n=(2000, 2000, 130)), "2^29"),
 ])
 def test_prepare_rejects_bad_boxes_without_touching_the_gpu(lib, kw, why):
     from paper_2210_17509_amd import grmhd as G

@@ -293,3 +293,69 @@ def test_c2p_atmosphere_and_failures(orc):
     Pr, Ur, st = orc.point_c2p(U, np.array([1, 0.1, 0, 0, 1, 0, 0, 0]), par)
     assert st in (2, 3)
     assert Pr[0] == par.rho_atm
+
+
+# ---------------------------------------------------------------- Newman-Hamlin map alone
+
+def _nh_cases():
+    """(P, Gamma, gamma_ij) of every Table I state and of random states in curved metrics
+    (general v and B, so S.B != 0 and every term of the cubic is exercised)."""
+    out = []
+    for t in _table1()["tests"].values():
+        for side in ("left", "right"):
+            out.append((_prim(t[side]), t["gamma"], (1.0, 0, 0, 1.0, 0, 1.0)))
+    rng = np.random.default_rng(517)
+    for k in range(24):
+        _, _, gs, g = _rand_metric(rng, shift=False)
+        out.append((_rand_prim(rng, g, vmax=0.95, bmax=2.0), 2.0 if k % 2 else 5.0 / 3.0, gs))
+    return out
+
+
+def test_nh_true_pressure_is_a_fixed_point(orc):
+    """Sec. II C's fallback maps a pressure to a new one through the largest root
+    x = z + B^2 of its cubic.  At the true pressure of a state the root must be the
+    true rho h W^2 + B^2, so the map returns that pressure, W and z.  The conserved
+    state comes from the stress-energy tensor path, not from the oracle's p2c."""
+    for P, gam, gs in _nh_cases():
+        U = orc.point_p2c(P, gam, 1.0, None, gs, tmunu=True)
+        p = (gam - 1.0) * P[0] * P[4]
+        W, _, _ = orc.point_lorentz(P, gam, g=gs)
+        z = (P[0] * (1.0 + P[4]) + p) * W * W
+        ok, pn, Wn, zn = orc.point_nh_map(U, p, _params(gam), gs)
+        assert ok
+        tol = 1e-12 * max(1.0, W * W / 4.0)  # 1 - v^2 is conditioned like W^2 (R20)
+        assert abs(pn - p) <= tol * p, (P, pn, p)
+        assert abs(Wn - W) <= tol * W
+        assert abs(zn - z) <= tol * z
+
+
+def test_nh_map_moves_a_wrong_pressure(orc):
+    """Away from the fixed point the map must move the pressure (a map that returned
+    its argument would pass the fixed-point pin)."""
+    for P, gam, gs in _nh_cases():
+        U = orc.point_p2c(P, gam, 1.0, None, gs, tmunu=True)
+        p = (gam - 1.0) * P[0] * P[4]
+        ok, pn, _, _ = orc.point_nh_map(U, 1.5 * p, _params(gam), gs)
+        if ok:
+            assert abs(pn - 1.5 * p) > 1e-6 * p
+
+
+def test_nh_iteration_alone_converges_from_rest(orc):
+    """The pressure iteration with its Aitken steps, without the 3D Newton polish,
+    reaches the true pressure from the at-rest guess con2prim uses when it has no
+    usable previous state: T = (Gamma - 1) (tau - B^2/2) / D, p = D T."""
+    for P, gam, gs in _nh_cases():
+        U = orc.point_p2c(P, gam, 1.0, None, gs, tmunu=True)
+        sg = np.sqrt(np.linalg.det(np.array([[gs[0], gs[1], gs[2]], [gs[1], gs[3], gs[4]], [gs[2], gs[4], gs[5]]])))
+        g3 = np.array([[gs[0], gs[1], gs[2]], [gs[1], gs[3], gs[4]], [gs[2], gs[4], gs[5]]])
+        D, tau, B = U[0] / sg, U[4] / sg, U[5:] / sg
+        B2 = B @ g3 @ B
+        T0 = (gam - 1.0) * max(tau - 0.5 * B2, 1e-10 * D) / D
+        p = (gam - 1.0) * P[0] * P[4]
+        W, _, _ = orc.point_lorentz(P, gam, g=gs)
+        ok, pr, Wr, zr, Tr = orc.point_nh_solve(U, D * T0, _params(gam), gs)
+        assert ok, P
+        tol = 1e-9 * max(1.0, W * W / 4.0)
+        assert abs(pr - p) <= tol * p, (P, pr, p)
+        assert abs(Wr - W) <= tol * W
+        assert abs(Tr - p / P[0]) <= tol * p / P[0]

@@ -323,3 +323,130 @@ def test_time_integrators_convergence_order(orc):
         e1 = np.abs(run(scheme, dt, 8) - ref).max()
         e2 = np.abs(run(scheme, dt / 2, 16) - ref).max()
         assert 0.9 * 2 ** order < e1 / e2 < 1.1 * 2 ** order, (scheme, e1, e2)
+
+
+# ---------------------------------------------------------------- max signal rate: closed forms
+
+def _rate(orc, prob):
+    U = orc.prim2con(prob)
+    P = prob.P.copy()
+    _, rate, nfail = orc.rhs(prob, U, P)
+    assert nfail == 0
+    return rate
+
+
+@pytest.mark.parametrize("v", [0.0, 0.3, -0.7])
+def test_max_rate_flat_hydro_closed_form(orc, v):
+    """B = 0, flow v along x, flat space: along x the signal bound is the relativistic
+    sum (|v| + c_s) / (1 + |v| c_s); across the flow it is the transverse sound speed
+    c_s sqrt(1 - v^2) / sqrt(1 - v^2 c_s^2).  The reported rate is the larger of each
+    over its own dx."""
+    gam, rho, eps = 5.0 / 3.0, 0.8, 1.1
+    p = (gam - 1) * rho * eps
+    cs = np.sqrt(gam * p / (rho * (1 + eps) + p))
+    dx = (0.1, 0.13, 0.07)
+    prob = T.build((5, 4, 6), T.uniform_fields([rho, v, 0, 0, eps, 0, 0, 0]), dx=dx,
+                   params=I.Params(recon=I.RECON_WENO5, eos_gamma=gam))
+    along = (abs(v) + cs) / (1 + abs(v) * cs)
+    across = cs * np.sqrt(1 - v * v) / np.sqrt(1 - v * v * cs * cs)
+    want = max(along / dx[0], across / dx[1], across / dx[2])
+    assert _rate(orc, prob) == pytest.approx(want, rel=1e-13)
+
+
+def test_max_rate_magnetised_rest_closed_form(orc):
+    """Fluid at rest with B perpendicular to x: the fast magnetosonic speed
+    sqrt((Gamma p + b^2) / (rho h + b^2)), b^2 = B^2; the bound of every direction
+    uses it (reading R5), so the rate is that speed over the smallest dx."""
+    gam, rho, eps, B = 2.0, 0.5, 0.9, (0.0, 0.8, -0.6)
+    p = (gam - 1) * rho * eps
+    b2 = B[1] ** 2 + B[2] ** 2
+    cf = np.sqrt((gam * p + b2) / (rho * (1 + eps) + p + b2))
+    dx = (0.1, 0.05, 0.2)
+    prob = T.build((4, 6, 5), T.uniform_fields([rho, 0, 0, 0, eps, *B]), dx=dx,
+                   params=I.Params(recon=I.RECON_MINMOD, eos_gamma=gam))
+    assert _rate(orc, prob) == pytest.approx(cf / dx[1], rel=1e-13)
+
+
+def test_max_rate_constant_metric_and_shift(orc):
+    """Constant lapse a0, gamma_ij = a^2 delta_ij and shift b along x, fluid at rest:
+    lambda+- = +-a0 c_s / a - beta^d, so max(xi+, -xi-) is a0 c_s / a + |b| along x and
+    a0 c_s / a along y and z."""
+    gam, rho, eps, a0, a, b = 5.0 / 3.0, 1.2, 0.6, 0.7, 1.3, 0.15
+    p = (gam - 1) * rho * eps
+    cs = np.sqrt(gam * p / (rho * (1 + eps) + p))
+    dx = (0.2, 0.17, 0.3)
+    met = T.conformal_metric(lambda X, Y, Z: np.sqrt(a) + 0 * X, alpha_fn=lambda X, Y, Z: a0 + 0 * X,
+                             beta_fn=lambda X, Y, Z: [b + 0 * X, 0 * X, 0 * X])
+    prob = T.build((5, 5, 4), T.uniform_fields([rho, 0, 0, 0, eps, 0, 0, 0]), met, dx=dx,
+                   params=I.Params(recon=I.RECON_WENO5, eos_gamma=gam))
+    c = a0 * cs / a
+    want = max((c + abs(b)) / dx[0], c / dx[1], c / dx[2])
+    assert _rate(orc, prob) == pytest.approx(want, rel=1e-13)
+
+
+# ---------------------------------------------------------------- boundary maps on boxes narrower than the ghosts
+
+@pytest.mark.parametrize("n,bc", [
+    ((1, 2, 3), (I.BC_PERIODIC,) * 6),
+    ((2, 1, 5), (I.BC_PERIODIC,) * 6),
+    ((3, 1, 2), (I.BC_OUTFLOW, I.BC_OUTFLOW, I.BC_PERIODIC, I.BC_PERIODIC, I.BC_OUTFLOW, I.BC_OUTFLOW)),
+])
+def test_ghost_maps_brute_force(orc, n, bc):
+    """Every ghost cell holds the interior cell the boundary rule names, checked
+    cell by cell: periodic wraps i -> i mod n (several times when n < 3), outflow
+    copies the nearest interior cell (Sec. IV A)."""
+    g = 3
+    spec = I.BoxSpec(n, g, bc, (0.0, 0.0, 0.0), (1.0, 1.0, 1.0))
+    NX, NY, NZ = (n[d] + 2 * g for d in range(3))
+    P = np.zeros((8, NZ * NY * NX))
+    rng = np.random.default_rng(5)
+    val = rng.normal(size=(8, n[2], n[1], n[0]))
+    Pv = P.reshape(8, NZ, NY, NX)
+    Pv[:, g:g + n[2], g:g + n[1], g:g + n[0]] = val
+    F = orc.fill_ghosts(spec, P).reshape(8, NZ, NY, NX)
+
+    def src(i, d):
+        if 0 <= i < n[d]:
+            return i
+        if bc[2 * d] == I.BC_PERIODIC:
+            return i % n[d]  # Python's mod is non-negative
+        return 0 if i < 0 else n[d] - 1
+
+    for k in range(-g, n[2] + g):
+        for j in range(-g, n[1] + g):
+            for i in range(-g, n[0] + g):
+                np.testing.assert_array_equal(F[:, k + g, j + g, i + g], val[:, src(k, 2), src(j, 1), src(i, 0)])
+
+
+@pytest.mark.parametrize("n", [(1, 2, 3), (2, 1, 5)])
+@pytest.mark.parametrize("recon", [I.RECON_MINMOD, I.RECON_WENO5])
+def test_uniform_state_on_boxes_narrower_than_ghosts(orc, n, recon):
+    state = [0.7, 0.3, -0.2, 0.1, 1.2, 0.5, -0.4, 0.8]
+    prob = T.build(n, T.uniform_fields(state), params=I.Params(recon=recon))
+    U0 = orc.prim2con(prob)
+    U = U0.copy()
+    orc.rk_step(prob, U, prob.P.copy())
+    np.testing.assert_array_equal(T.interior(prob, U), T.interior(prob, U0))
+
+
+@pytest.mark.parametrize("ny,nz", [(2, 1), (3, 2)])
+def test_transverse_copies_equal_one_dimensional_run(orc, ny, nz):
+    """Data uniform in y and z on an (N, ny, nz) periodic box evolve exactly as on an
+    (N, 1, 1) box: every y and z face sees the same state on both sides, whatever
+    the wrapped ghost indices are, so each transverse column repeats the 1D run bit
+    for bit."""
+    def f(X, Y, Z):
+        s = np.sin(2 * np.pi * X)
+        return [1 + 0.3 * s, 0.2 + 0.1 * s, -0.1 * s, 0.05 + 0 * X, 1.0 + 0.2 * np.cos(2 * np.pi * X),
+                0.4 + 0 * X, 0.3 * s, -0.2 + 0 * X]
+    par = I.Params(recon=I.RECON_WENO5)
+    one = T.build((16, 1, 1), f, dx=(1 / 16, 0.1, 0.1), params=par)
+    many = T.build((16, ny, nz), f, dx=(1 / 16, 0.1, 0.1), params=par)
+    res = []
+    for prob in (one, many):
+        U = orc.prim2con(prob)
+        orc.rk_step(prob, U, prob.P.copy(), steps=2)
+        res.append(T.interior(prob, U))
+    for k in range(nz):
+        for j in range(ny):
+            np.testing.assert_array_equal(res[1][:, k, j, :], res[0][:, 0, 0, :])
