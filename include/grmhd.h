@@ -13,7 +13,8 @@
  * arguments on the host, enqueues its kernels on `stream` (a hipStream_t,
  * NULL = the null stream) and returns without synchronizing.  The library
  * keeps no pointer after a call returns and allocates no device memory in
- * these calls; scratch memory comes from the caller's workspace `ws`.
+ * these calls; scratch memory comes from the caller's workspace `ws` (or, for
+ * grmhd_rk_step_noalloc, from a fixed array the library holds per device).
  *
  * Grid.  A problem is a list of boxes (a single grid is one box).  Each box
  * has n[d] interior cells per axis and ng >= 3 ghost layers (ng >= 2 is
@@ -190,6 +191,25 @@ int grmhd_rhs(const grmhd_domain* dom, const grmhd_params* par, const grmhd_metr
 int grmhd_rk_step(const grmhd_domain* dom, const grmhd_params* par, const grmhd_metric* met,
                   double* U, double* P, double dt, int32_t scheme, double* stage_ckpt,
                   double* max_rate, int64_t* n_fail, void* ws, size_t ws_bytes, void* stream);
+
+/* grmhd_rk_step for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same step, bit for bit, with the workspace taken from a fixed array
+ * that the library holds on every device it runs on, for the life of the
+ * process, instead of the caller's ws.  The call itself allocates nothing.
+ * Limit: grmhd_workspace_bytes(dom, par, scheme, 0) must not exceed
+ * GRMHD_NOALLOC_SCRATCH_BYTES (256 MiB: about 1.39 M cells with ghosts for
+ * SSPRK3 with p_current = 1 or RK4, 2.09 M otherwise, e.g. a 105^3 or a
+ * 121^3 box with 3 ghost layers); larger domains get GRMHD_EWORKSPACE and
+ * nothing is enqueued.  All calls on one device share that device's array and
+ * leave it dirty; the step writes every scratch value before reading it.
+ * Calls that overlap on one device (concurrent streams or threads) race on the
+ * array and must be serialized by the caller.  The current device must be the
+ * one `stream` belongs to.  Other arguments and errors as grmhd_rk_step. */
+#define GRMHD_NOALLOC_SCRATCH_BYTES (256u << 20)
+int grmhd_rk_step_noalloc(const grmhd_domain* dom, const grmhd_params* par, const grmhd_metric* met, double* U,
+                          double* P, double dt, int32_t scheme, double* stage_ckpt, double* max_rate,
+                          int64_t* n_fail, void* stream);
 
 /* Vector-Jacobian product of con2prim on interior cells: gU = (dP/dU)^T gP,
  * through the implicit-function theorem (con2prim inverts Eqs. (p2c1)-(p2c4),

@@ -1250,6 +1250,34 @@ hipError_t launch_adj_cell(const AdjCellArgs& a, const Prepared& pr, hipStream_t
   return hipGetLastError();
 }
 
+// ---- fixed scratch of grmhd_rk_step_noalloc ----
+// The step's workspace for callers that cannot allocate: one array per device,
+// held for the life of the process.  Host code never uses the array's name as
+// a device address; it takes the address hipGetSymbolAddress returns for the
+// current device, once per device.
+__device__ __align__(256) unsigned char scratch[GRMHD_NOALLOC_SCRATCH_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+std::mutex g_scratch_mu;
+
+int scratch_address(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail_hip(e, "hipGetDevice");
+  if (dev < 0 || dev >= MAX_DEVICES) return invalid("device index beyond the scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return fail_hip(e, "hipGetSymbolAddress(scratch)");
+    if (!p) return fail_hip(hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch) returned null");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return GRMHD_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1430,9 +1458,10 @@ static int rk4_step(const grmhd_domain* dom, const Prepared& pr, const KPhys& ph
   return e == hipSuccess ? GRMHD_OK : fail_hip(e, "k_con2prim");
 }
 
-int grmhd_rk_step(const grmhd_domain* dom, const grmhd_params* par, const grmhd_metric* met, double* U, double* P,
-                  double dt, int32_t scheme, double* stage_ckpt, double* max_rate, int64_t* n_fail, void* ws,
-                  size_t ws_bytes, void* stream) {
+// One step of grmhd_rk_step with the workspace ws (ws_bytes bytes).
+static int rk_step_impl(const grmhd_domain* dom, const grmhd_params* par, const grmhd_metric* met, double* U,
+                        double* P, double dt, int32_t scheme, double* stage_ckpt, double* max_rate, int64_t* n_fail,
+                        void* ws, size_t ws_bytes, void* stream) {
   Prepared pr;
   KPhys ph;
   int r;
@@ -1496,6 +1525,31 @@ int grmhd_rk_step(const grmhd_domain* dom, const grmhd_params* par, const grmhd_
     Pcur = a.Pout;
   }
   return GRMHD_OK;
+}
+
+int grmhd_rk_step(const grmhd_domain* dom, const grmhd_params* par, const grmhd_metric* met, double* U, double* P,
+                  double dt, int32_t scheme, double* stage_ckpt, double* max_rate, int64_t* n_fail, void* ws,
+                  size_t ws_bytes, void* stream) {
+  return rk_step_impl(dom, par, met, U, P, dt, scheme, stage_ckpt, max_rate, n_fail, ws, ws_bytes, stream);
+}
+
+int grmhd_rk_step_noalloc(const grmhd_domain* dom, const grmhd_params* par, const grmhd_metric* met, double* U,
+                          double* P, double dt, int32_t scheme, double* stage_ckpt, double* max_rate, int64_t* n_fail,
+                          void* stream) {
+  if (!dom || dom->cell_stride < 1) return invalid("null domain or bad cell stride");
+  const size_t need = grmhd_workspace_bytes(dom, par, scheme, 0);
+  if (need > (size_t)GRMHD_NOALLOC_SCRATCH_BYTES) {
+    g_last_error = "grmhd_rk_step_noalloc: the step needs " + std::to_string(need) +
+                   " bytes of scratch, more than the library's fixed " +
+                   std::to_string((size_t)GRMHD_NOALLOC_SCRATCH_BYTES) +
+                   " bytes (use grmhd_rk_step with a caller workspace)";
+    return GRMHD_EWORKSPACE;
+  }
+  void* ws = nullptr;
+  const int r = scratch_address(&ws);
+  if (r) return r;
+  return rk_step_impl(dom, par, met, U, P, dt, scheme, stage_ckpt, max_rate, n_fail, ws,
+                      (size_t)GRMHD_NOALLOC_SCRATCH_BYTES, stream);
 }
 
 

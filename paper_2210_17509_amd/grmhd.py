@@ -61,6 +61,7 @@ _lib.grmhd_con2prim.argtypes = [_pd, _pp, _pm, _P, _P, _P, _P, _P]
 _lib.grmhd_rhs.argtypes = [_pd, _pp, _pm, _P, _P, _P, _P, _P, _P]
 _lib.grmhd_rk_step.argtypes = [_pd, _pp, _pm, _P, _P, ctypes.c_double, ctypes.c_int32, _P, _P, _P, _P,
                                ctypes.c_size_t, _P]
+_lib.grmhd_rk_step_noalloc.argtypes = [_pd, _pp, _pm, _P, _P, ctypes.c_double, ctypes.c_int32, _P, _P, _P, _P]
 _lib.grmhd_workspace_bytes.argtypes = [_pd, _pp, ctypes.c_int32, ctypes.c_int32]
 _lib.grmhd_workspace_bytes.restype = ctypes.c_size_t
 _lib.grmhd_strerror.argtypes = [ctypes.c_int]
@@ -74,7 +75,9 @@ _lib.grmhd_timing_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINT
 
 EXPORTED = ["grmhd_domain_table_bytes", "grmhd_domain_prepare", "grmhd_prim2con", "grmhd_con2prim", "grmhd_rhs",
             "grmhd_rk_step", "grmhd_workspace_bytes", "grmhd_strerror", "grmhd_last_error", "grmhd_timing_enable",
-            "grmhd_timing_read", "grmhd_con2prim_adjoint", "grmhd_rk_step_adjoint"]
+            "grmhd_timing_read", "grmhd_con2prim_adjoint", "grmhd_rk_step_adjoint", "grmhd_rk_step_noalloc"]
+
+GRMHD_NOALLOC_SCRATCH_BYTES = 256 << 20  # the fixed scratch of grmhd_rk_step_noalloc
 
 
 class GrmhdError(RuntimeError):
@@ -215,6 +218,13 @@ def grmhd_rk_step(dom, params, met, U, P, dt, scheme=GRMHD_SSPRK3, stage_ckpt=No
                               ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(ws.numel() * ws.element_size()),
                               _stream(stream)))
     return ws
+
+
+def grmhd_rk_step_noalloc(dom, params, met, U, P, dt, scheme=GRMHD_SSPRK3, stage_ckpt=None, max_rate=None,
+                          n_fail=None, stream=None):
+    _check(_lib.grmhd_rk_step_noalloc(ctypes.byref(dom.c), ctypes.byref(_par(params)), ctypes.byref(met.c), _ptr(U),
+                                      _ptr(P), float(dt), int(scheme), _ptr(stage_ckpt), _ptr(max_rate),
+                                      _ptr(n_fail, torch.int64), _stream(stream)))
 
 
 def grmhd_timing_enable(on=True):
