@@ -375,9 +375,11 @@ def adjoint_bench(args):
                        "cells": ncell}}
 
 
-def run_workload(name, args):
+def run_workload(name, args, steps=None, warmup=None):
     """Warm up, then time `steps` SSPRK3 steps of workload `name` (HIP events on every
     stage and con2prim launch, wall clock around the whole timed region)."""
+    steps = args.steps if steps is None else steps
+    warmup = args.warmup if warmup is None else warmup
     import torch
     from paper_2210_17509_amd import grmhd as G
     prob = make_problem(name)
@@ -397,13 +399,13 @@ def run_workload(name, args):
         par, _ = autotune(dom, par, met, U, P, prob.dt, reps=2)
     scheme = WORKLOADS[name].get("scheme", G.GRMHD_SSPRK3)
     ws = torch.empty(G.grmhd_workspace_bytes(dom, par, scheme) // 8, dtype=torch.float64, device="cuda")
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         G.grmhd_rk_step(dom, par, met, U, P, prob.dt, scheme, max_rate=rate, n_fail=nfail, ws=ws)
     torch.cuda.synchronize()
     G.grmhd_timing_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         G.grmhd_rk_step(dom, par, met, U, P, prob.dt, scheme, max_rate=rate, n_fail=nfail, ws=ws)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -411,6 +413,58 @@ def run_workload(name, args):
     G.grmhd_timing_enable(False)
     return {"prob": prob, "ncell": prob.ninterior, "wall": wall, "times": times, "nfail": int(nfail.item()),
             "par": par, "U": U, "P": P, "stages": {G.GRMHD_SSPRK3: 3, G.GRMHD_SSPRK2: 2, G.GRMHD_RK4: 4}[scheme]}
+
+
+def batched_bench(args, single_value):
+    """The 400-box batch stepped as a captured graph of one SSPRK3 step (tile shape and
+    schedule autotuned), timed over `steps` replays; its zone rate against the single
+    256^3 box of the headline."""
+    import torch
+    from paper_2210_17509_amd import grmhd as G
+    from paper_2210_17509_amd.autotune import StepGraph, autotune
+    prob = make_problem("batched400")
+    dom = G.Domain.from_problem(prob)
+    met = G.Metric.from_problem(prob)
+    par = G.make_params(prob.params, p_current=1)
+    P = torch.as_tensor(prob.P, device="cuda").contiguous()
+    U = torch.zeros_like(P)
+    nfail = torch.zeros(1, dtype=torch.int64, device="cuda")
+    rate = torch.zeros(1, dtype=torch.float64, device="cuda")
+    G.grmhd_prim2con(dom, par, met, P, U)
+    par, _ = autotune(dom, par, met, U, P, prob.dt, reps=2)
+    graph = StepGraph(dom, par, met, U, P, prob.dt, max_rate=rate, n_fail=nfail)
+    for _ in range(args.warmup):
+        graph.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        graph.replay()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    value = prob.ninterior * 3 * args.steps / wall
+    return {"workload": WORKLOADS["batched400"]["desc"] + ", one captured graph per step", "value": value,
+            "unit": "zone-updates/s per RK stage", "ratio_to_single_box": value / single_value,
+            "cells": prob.ninterior, "boxes": len(prob.boxes), "tile": par.tile, "schedule": par.schedule,
+            "ms_per_step": wall * 1e3 / args.steps, "n_fail": int(nfail.item())}
+
+
+def mixed_bench(args, steps=50):
+    """The mixed-precision workload (384^3, FP32 reconstruction + HLLE) and the same
+    recipe in FP64, `steps` SSPRK3 steps each from the same initial data: both zone
+    rates, their ratio, and the per-field error of the mixed run against the FP64 run."""
+    fp = run_workload("curved384-fp64", args, steps=steps, warmup=0)
+    mx = run_workload("curved384-mixed", args, steps=steps, warmup=0)
+    vf = fp["ncell"] * 3 * steps / fp["wall"]
+    vm = mx["ncell"] * 3 * steps / mx["wall"]
+    out = {"workload": WORKLOADS["curved384-mixed"]["desc"] + f", {steps} SSPRK3 steps", "value": vm,
+           "fp64_value": vf, "ratio_mixed_over_fp64": vm / vf, "unit": "zone-updates/s per RK stage",
+           "n_fail": [fp["nfail"], mx["nfail"]],
+           "stage_ms_avg": {"fp64": fp["times"]["stage"][0] / max(fp["times"]["stage"][1], 1),
+                            "mixed": mx["times"]["stage"][0] / max(mx["times"]["stage"][1], 1)},
+           "U_error_vs_fp64": field_errors(mx["prob"], mx["U"], fp["U"]),
+           "P_error_vs_fp64": field_errors(mx["prob"], mx["P"], fp["P"])}
+    del fp, mx
+    return out
 
 
 def field_errors(prob, a, b):
@@ -440,6 +494,8 @@ def main():
     ap.add_argument("--adjoint", action="store_true",
                     help="adjoint workload: 128^3 WENO5-Z, 10 steps with checkpoints, then the reverse pass")
     ap.add_argument("--no-adjoint", action="store_true", help="leave the adjoint/forward ratio out of the line")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="leave the batched (400 boxes, graph) and mixed-precision (384^3, 50 steps) figures out")
     ap.add_argument("--hbm-summary", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
                     help="write profiles/k_stage_<workload>_hbm.txt from rocprofv3 --pmc output folders")
     ap.add_argument("--stats-summary", nargs=2, metavar=("STATS_DIR", "COMMAND"),
@@ -523,6 +579,9 @@ def main():
             out["compare"]["P_error_vs_compare"] = field_errors(prob, res["P"], ref["P"])
         del ref
     del res
+    if not args.no_extras and args.workload == "curved256":
+        out["batched"] = batched_bench(args, value)
+        out["mixed_precision"] = mixed_bench(args)
     if not args.no_adjoint:
         a = adjoint_bench(args)
         out["adjoint_forward_ratio"] = a["value"]
