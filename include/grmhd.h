@@ -114,8 +114,7 @@ typedef struct {
   int32_t precision;  /* GRMHD_FP64 | GRMHD_MIXED */
   int32_t wenoz_p;    /* WENO-Z exponent: 1 or 2 */
   int32_t c2p_maxit;  /* iteration cap of each con2prim method, e.g. 100 */
-  int32_t tile;       /* stage-kernel tile shape: -1 = library choice (16x4x3 for FP64, 16x4x4 for
-                       * mixed precision), else 0 .. GRMHD_NTILE-1 */
+  int32_t tile;       /* stage-kernel tile shape: -1 = library choice (16x4x3), else 0 .. GRMHD_NTILE-1 */
   int32_t schedule;   /* GRMHD_SCHED_GRID | GRMHD_SCHED_QUEUE (grmhd_rk_step only) */
   int32_t p_current;  /* grmhd_rk_step only: 0 = start with con2prim(U^n); 1 = P already holds the
                        * primitives of U^n (as the previous grmhd_rk_step, grmhd_con2prim or the

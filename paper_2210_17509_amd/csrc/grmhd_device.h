@@ -428,10 +428,10 @@ __device__ __forceinline__ void centre_inverse(CentreMetric& m) {
   const double cyz = g[1] * g[2] - g[0] * g[4];
   const double czz = g[0] * g[3] - g[1] * g[1];
   const double det = g[0] * cxx + g[1] * cxy + g[2] * cxz;
-  const double id = 1.0 / det;
+  const double id = rcp_r(det);
   m.gi[0] = cxx * id; m.gi[1] = cxy * id; m.gi[2] = cxz * id;
   m.gi[3] = cyy * id; m.gi[4] = cyz * id; m.gi[5] = czz * id;
-  m.sqrtg = sqrt(det);
+  m.sqrtg = sqrt_r(det);
 }
 
 // Cell-centre metric: mean of the cell's 8 vertices; inverse and sqrt(gamma)
@@ -714,9 +714,9 @@ __device__ bool c2p_newton(const C2PIn& c, const KPhys& ph, double& W, double& z
   const double SB2 = c.SB * c.SB;
   for (int it = 0; it < ph.c2p_maxit; ++it) {
     const double zB = z + c.B2;
-    const double iW = 1.0 / W;
+    const double iW = rcp_r(W);
     const double iW2 = iW * iW;
-    const double iz = 1.0 / z;
+    const double iz = rcp_r(z);
     const double iz2 = iz * iz;
     const double om = 1.0 - iW2;
     const double f1 = c.S2 - zB * zB * om + SB2 * (2.0 * z + c.B2) * iz2;
@@ -734,7 +734,8 @@ __device__ bool c2p_newton(const C2PIn& c, const KPhys& ph, double& W, double& z
     const double m1 = J22 * J33 - J23;        // minor of J11
     const double m2 = J21 * J33 - J23 * J31;  // minor of J12
     const double det = J11 * m1 - J12 * m2;
-    const double id = 1.0 / det;
+    if (!(det != 0.0) || !dfinite(det)) return false;
+    const double id = rcp_r(det);
     const double r1 = -f1, r2 = -f2, r3 = -f3;
     const double d1 = (r1 * m1 - J12 * (r2 * J33 - J23 * r3)) * id;
     const double d2 = (J11 * (r2 * J33 - J23 * r3) - r1 * m2) * id;
@@ -743,8 +744,9 @@ __device__ bool c2p_newton(const C2PIn& c, const KPhys& ph, double& W, double& z
     z += d2;
     T += d3;
     if (!(dfinite(W) && dfinite(z) && dfinite(T))) return false;
-    const double err = fmax(fabs(d1 / W), fmax(fabs(d2 / z), fabs(d3 / T)));
-    if (err < ph.c2p_tol) return true;
+    // max_k |dx_k / x_k| < tol, without divisions
+    const double tol = ph.c2p_tol;
+    if (fabs(d1) < tol * fabs(W) && fabs(d2) < tol * fabs(z) && fabs(d3) < tol * fabs(T)) return true;
   }
   return false;
 }
@@ -802,8 +804,8 @@ __device__ bool c2p_newman(const C2PIn& c, const KPhys& ph, double p0, double& W
 
 __device__ int c2p_recover(const C2PIn& c, const double* g, const double* gi, double gm1, double W, double z, double T,
                            double* P) {
-  const double izB = 1.0 / (z + c.B2);
-  const double sbz = c.SB / z;
+  const double izB = rcp_r(z + c.B2);
+  const double sbz = c.SB * rcp_r(z);
   double vlow[3], v[3];
 #pragma unroll
   for (int j = 0; j < 3; ++j)
@@ -811,7 +813,7 @@ __device__ int c2p_recover(const C2PIn& c, const double* g, const double* gi, do
 #pragma unroll
   for (int i = 0; i < 3; ++i) v[i] = gi[sidx(i, 0)] * vlow[0] + gi[sidx(i, 1)] * vlow[1] + gi[sidx(i, 2)] * vlow[2];
   const double v2 = vlow[0] * v[0] + vlow[1] * v[1] + vlow[2] * v[2];
-  const double rho = c.Dt / W;
+  const double rho = c.Dt * rcp_r(W);
   if (!(W >= 1.0) || !(z > 0.0) || !(T > 0.0) || !(rho > 0.0) || !(v2 < 1.0)) return C2P_UNPHYS;
   P[0] = rho;
   P[1] = v[0];
@@ -846,7 +848,7 @@ __device__ int c2p_cell(const double* g, const double* gi, double sqrtg, const K
     c2p_atmosphere(g, sqrtg, ph, U, P);
     return C2P_NONFINITE;
   }
-  const double is = 1.0 / sqrtg;
+  const double is = rcp_r(sqrtg);
   C2PIn c;
   c.Dt = U[0] * is;
   if (c.Dt < ph.rho_atm) {
@@ -879,7 +881,7 @@ __device__ int c2p_cell(const double* g, const double* gi, double sqrtg, const K
       for (int j = 0; j < 3; ++j) v2 += g[sidx(i, j)] * P[1 + i] * P[1 + j];
     const bool ok = dfinite(v2) && v2 < 1.0 && P[0] > 0.0 && P[4] > 0.0 && dfinite(P[0]) && dfinite(P[4]);
     if (ok) {
-      W = 1.0 / sqrt(1.0 - v2);
+      W = rcp_r(sqrt_r(1.0 - v2));
       p0 = ph.gm1 * P[0] * P[4];
       z = (P[0] + P[0] * P[4] + p0) * W * W;
       T = p0 / P[0];
