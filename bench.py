@@ -107,14 +107,18 @@ def cpu_baseline(w, budget_s=12.0):
             "sample": f"one SSPRK3 step of the same recipe on {n}^3 cells ({t:.1f} s wall, {threads} threads)"}
 
 
-KERNEL_SOURCES = ("paper_2210_17509_amd/csrc/grmhd_capi.hip", "paper_2210_17509_amd/csrc/grmhd_device.h",
-                  "paper_2210_17509_amd/csrc/grmhd_adjoint.h", "include/grmhd.h")
+def kernel_sources():
+    """Every source the HIP library is built from (csrc/*.hip, csrc/*.h, the C header)."""
+    import glob
+    csrc = sorted(glob.glob(os.path.join(ROOT, "paper_2210_17509_amd", "csrc", "*.hip")) +
+                  glob.glob(os.path.join(ROOT, "paper_2210_17509_amd", "csrc", "*.h")))
+    return [os.path.relpath(f, ROOT) for f in csrc] + ["include/grmhd.h"]
 
 
 def kernel_source_hash():
     import hashlib
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in kernel_sources():
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()

@@ -85,6 +85,11 @@ def lib():
         L.orc_point_nh_solve.argtypes = [_D, _D, pp, ctypes.c_double, _D]
         L.orc_point_nh_solve.restype = ctypes.c_int
         L.orc_fill_ghosts.argtypes = [pb, _D]
+        L.orc_ct_init.argtypes = [pb, _D, _D, _D, _D, _D, _D]
+        L.orc_ct_face_field.argtypes = [pb, _D, _D]
+        L.orc_ct_step.argtypes = [pb, pp, _D, _D, _D, _D, _D, _D, ctypes.c_double, ctypes.c_int, ctypes.c_int, _D]
+        L.orc_ct_step.restype = ctypes.c_long
+        L.orc_ct_edge_rhs.argtypes = [pb, pp, _D, _D, _D, _D, _D]
         _lib = L
     return _lib
 
@@ -348,3 +353,70 @@ def count_ops(recon):
     out = (ctypes.c_long * 8)()
     lib().orc_count_ops(int(recon), out)
     return {"face": tuple(out[0:4]), "cell": tuple(out[4:8])}
+
+
+# ---------------------------------------------------------------- constrained transport (Sec. III B)
+#
+# A: (3, vert_stride) edge fields (A_x, A_y, A_z), each box's edges stored like its
+# vertex metric; A_e of an edge along e sits at the vertex-shaped index with the
+# cell index along e in place of that vertex index.
+
+def _box_verts(prob, arr, b):
+    bx = prob.boxes[b]
+    v0 = prob.vert_off[b]
+    return np.ascontiguousarray(arr[:, v0:v0 + bx.nvert])
+
+
+def ct_init(prob, A, P):
+    """Initial data with constrained transport: P's B from the cell-centred Bcal =
+    curl A, then U from P.  P is updated in place; returns U."""
+    L = lib()
+    for b, bx in enumerate(prob.boxes):
+        a, be, g = _box_metric(prob, b)
+        Ab, Pb = _box_verts(prob, A, b), _box_cells(prob, P, b)
+        Ub = np.zeros_like(Pb)
+        L.orc_ct_init(ctypes.byref(make_box(bx)), _p(a), _p(be), _p(g), _p(Ab), _p(Ub), _p(Pb))
+        c0 = prob.cell_off[b]
+        P[:, c0:c0 + bx.ncell] = Pb
+    return prim2con(prob, P)
+
+
+def ct_face_field(prob, A, b=0):
+    """Face field Bcal = curl A of box b: (3, ncell) cell-shaped arrays; the d-face at
+    vertex index m along d sits at the cell index m (m = n in the first ghost cell)."""
+    bx = prob.boxes[b]
+    out = np.zeros((3, bx.ncell))
+    lib().orc_ct_face_field(ctypes.byref(make_box(bx)), _p(_box_verts(prob, A, b)), _p(out))
+    return out
+
+
+def ct_edge_rhs(prob, P, b=0):
+    """dA/dt of box b from primitives P (the magnetic face fluxes of their RHS)."""
+    bx = prob.boxes[b]
+    a, be, g = _box_metric(prob, b)
+    Pb = _box_cells(prob, P, b)
+    dA = np.zeros((3, bx.nvert))
+    lib().orc_ct_edge_rhs(ctypes.byref(make_box(bx)), ctypes.byref(make_par(prob.params)), _p(a), _p(be), _p(g),
+                          _p(Pb), _p(dA))
+    return dA
+
+
+def ct_rk_step(prob, U, P, A, dt=None, scheme=0, steps=1, p_current=0):
+    """In-place RK steps with constrained transport (U, P, A); returns (max_rate, n_fail)."""
+    L = lib()
+    par = make_par(prob.params)
+    dt = prob.dt if dt is None else dt
+    rate = ctypes.c_double(0.0)
+    nfail = 0
+    for b, bx in enumerate(prob.boxes):
+        a, be, g = _box_metric(prob, b)
+        Ub, Pb, Ab = _box_cells(prob, U, b), _box_cells(prob, P, b), _box_verts(prob, A, b)
+        for k in range(steps):
+            nfail += L.orc_ct_step(ctypes.byref(make_box(bx)), ctypes.byref(par), _p(a), _p(be), _p(g), _p(Ub),
+                                   _p(Pb), _p(Ab), float(dt), int(scheme), int(p_current),
+                                   ctypes.byref(rate))
+        c0, v0 = prob.cell_off[b], prob.vert_off[b]
+        U[:, c0:c0 + bx.ncell] = Ub
+        P[:, c0:c0 + bx.ncell] = Pb
+        A[:, v0:v0 + bx.nvert] = Ab
+    return rate.value, nfail

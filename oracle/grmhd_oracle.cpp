@@ -1021,7 +1021,16 @@ template <class T> void prim2con_box(const Box& bx, const Par& par, const VMetri
 
 // RHS from given primitives (steps 2-4 of the paper's RHS evaluation):
 // dUdt = -sum_d (F_{+1/2} - F_{-1/2}) / dx_d + S on interior cells.
-template <class T> void rhs_from_prims(const Box& bx, const Par& par, const VMetric& vm, T* P, T* dUdt, double* max_rate) {
+// Face fluxes of the magnetic field components, kept for constrained transport:
+// f[d][c * nface_d + fi] = the HLLE flux through d-faces of Bcal^c, fi = face
+// index (k * nf_y + j) * nf_x + i over the face grid of direction d.
+template <class T> struct MagFlux {
+  std::vector<T> f[3];
+  long nf[3][3];
+};
+
+template <class T> void rhs_from_prims(const Box& bx, const Par& par, const VMetric& vm, T* P, T* dUdt, double* max_rate,
+                                       MagFlux<T>* mf = nullptr) {
   Geo G(bx);
   fill_ghosts(bx, G, P);
   for (int q = 0; q < 8; ++q)
@@ -1074,6 +1083,10 @@ template <class T> void rhs_from_prims(const Box& bx, const Par& par, const VMet
           drate = std::max(drate, r);
         }
     rate = std::max(rate, drate);
+    if (mf) {
+      for (int e = 0; e < 3; ++e) mf->nf[d][e] = nf[e];
+      mf->f[d].assign(F.begin() + 5 * nface, F.begin() + 8 * nface);
+    }
 #pragma omp parallel for schedule(static) num_threads(nthreads_req)
     for (long k = 0; k < G.n[2]; ++k)
       for (long j = 0; j < G.n[1]; ++j)
@@ -1143,6 +1156,151 @@ template <class T> long rk_step_box(const Box& bx, const Par& par, const VMetric
             long x = q * G.ncell + G.c(i, j, k);
             U[x] = Un[x] + cs[s] * ((U[x] - Un[x]) + dt * L[x]);
           }
+  }
+  nfail += con2prim_box(bx, par, vm, U, P, (int32_t*)nullptr);
+  return nfail;
+}
+
+/* ------------------------------------------------------------------------ */
+/* constrained transport (Sec. III B: vector potential on cell edges)       */
+/* ------------------------------------------------------------------------ */
+//
+// A_e lives on the edges along axis e: at cell index c_e along e and vertex
+// indices along the two other axes, stored like a vertex field (index
+// G.v(i, j, k) with the cell index along e in place of that vertex index).
+// The face field is Bcal = curl A (Bcal^d = d_a A_b - d_b A_a, a = d+1, b = d+2
+// cyclic), so its discrete divergence vanishes identically; the cell-centred
+// Bcal entering U is the mean of a cell's two d-face values.  The induction
+// equation d_t Bcal^d + d_j F^j(Bcal^d) = 0 follows from d_t A_e = F^a(Bcal^b)
+// = -F^b(Bcal^a) (the flux is antisymmetric): at an edge each of the two is the
+// mean of the HLLE fluxes on the two faces beside it, and the edge value is
+// their mean (R28).  The gauge term of the potential is a gradient, which curl
+// removes: it is left out.
+
+// vertex-shaped storage index of grid point (x, y, z) (cell or vertex indices)
+static long vidx(const Geo& G, long x, long y, long z) { return G.v(x, y, z); }
+
+// face index of the d-face with (i, j, k) on the face grid nf[d]
+template <class T> static long face_at(const MagFlux<T>& mf, int d, long i, long j, long k) {
+  return (k * mf.nf[d][1] + j) * mf.nf[d][0] + i;
+}
+
+// interior cell index along an axis for a transverse neighbour just outside the
+// box (the boundary map of the primitives: the fluxes of a ghost column are
+// those of the column it copies)
+static long col_map(const Box& bx, int axis, long c) { return bc_map(c, bx.n[axis], bx.bc[2 * axis], bx.bc[2 * axis + 1]); }
+
+// dA/dt on every interior edge from the magnetic face fluxes.
+template <class T> void ct_edge_rhs(const Box& bx, const MagFlux<T>& mf, T* dA) {
+  Geo G(bx);
+  for (int q = 0; q < 3; ++q)
+    for (long x = 0; x < G.nvert; ++x) dA[q * G.nvert + x] = T(0.0);
+  for (int e = 0; e < 3; ++e) {
+    const int a = (e + 1) % 3, b = (e + 2) % 3;
+    long hi[3];
+    for (int d = 0; d < 3; ++d) hi[d] = (d == e) ? bx.n[d] : bx.n[d] + 1;
+    for (long z = 0; z < hi[2]; ++z)
+      for (long y = 0; y < hi[1]; ++y)
+        for (long x = 0; x < hi[0]; ++x) {
+          const long p[3] = {x, y, z};
+          // F^a(Bcal^b) on the a-faces at vertex p[a] along a, cells p[b]-1 and p[b] along b
+          T fa = T(0.0), fb = T(0.0);
+          for (int side = 0; side < 2; ++side) {
+            long c[3] = {p[0], p[1], p[2]};
+            c[b] = col_map(bx, b, p[b] - 1 + side);
+            fa = fa + mf.f[a][b * (mf.nf[a][0] * mf.nf[a][1] * mf.nf[a][2]) + face_at(mf, a, c[0], c[1], c[2])];
+            long c2[3] = {p[0], p[1], p[2]};
+            c2[a] = col_map(bx, a, p[a] - 1 + side);
+            fb = fb + mf.f[b][a * (mf.nf[b][0] * mf.nf[b][1] * mf.nf[b][2]) + face_at(mf, b, c2[0], c2[1], c2[2])];
+          }
+          dA[e * G.nvert + vidx(G, x, y, z)] = 0.5 * (0.5 * fa - 0.5 * fb);
+        }
+  }
+}
+
+// Face field Bcal^d on every interior d-face: out[d * G.ncell + G.c(i, j, k)] for
+// the d-face at vertex index (i, j, k)[d] along d (cell-shaped storage; the face
+// at n along d sits in the first ghost cell).
+template <class T> void ct_face_field(const Box& bx, const T* A, T* out) {
+  Geo G(bx);
+  for (int d = 0; d < 3; ++d) {
+    const int a = (d + 1) % 3, b = (d + 2) % 3;
+    long hi[3] = {bx.n[0], bx.n[1], bx.n[2]};
+    hi[d] += 1;
+    for (long k = 0; k < hi[2]; ++k)
+      for (long j = 0; j < hi[1]; ++j)
+        for (long i = 0; i < hi[0]; ++i) {
+          const long p[3] = {i, j, k};
+          long pa[3] = {i, j, k}, pb[3] = {i, j, k};
+          pa[a] += 1;  // the b-edge one vertex up along a
+          pb[b] += 1;  // the a-edge one vertex up along b
+          const T dAb = A[b * G.nvert + vidx(G, pa[0], pa[1], pa[2])] - A[b * G.nvert + vidx(G, p[0], p[1], p[2])];
+          const T dAa = A[a * G.nvert + vidx(G, pb[0], pb[1], pb[2])] - A[a * G.nvert + vidx(G, p[0], p[1], p[2])];
+          out[d * G.ncell + G.c(i, j, k)] = dAb / bx.dx[a] - dAa / bx.dx[b];
+        }
+  }
+}
+
+// U's Bcal (fields 5..7) on interior cells from A: the mean of the two face values.
+template <class T> void ct_cell_field(const Box& bx, const T* A, T* U) {
+  Geo G(bx);
+  std::vector<T> Bf(3 * G.ncell);
+  ct_face_field(bx, A, Bf.data());
+  for (int d = 0; d < 3; ++d) {
+    long up[3] = {0, 0, 0};
+    up[d] = 1;
+    for (long k = 0; k < bx.n[2]; ++k)
+      for (long j = 0; j < bx.n[1]; ++j)
+        for (long i = 0; i < bx.n[0]; ++i)
+          U[(5 + d) * G.ncell + G.c(i, j, k)] =
+              0.5 * (Bf[d * G.ncell + G.c(i, j, k)] + Bf[d * G.ncell + G.c(i + up[0], j + up[1], k + up[2])]);
+  }
+}
+
+// One method-of-lines step with constrained transport: U^n's Bcal from A^n,
+// con2prim (unless p_current), then per stage the RHS of U (its Bcal components
+// are replaced), dA/dt from the stage's magnetic face fluxes, the same stage
+// combine for U and A, and U_{s+1}'s Bcal from A_{s+1} before its con2prim.
+template <class T> long ct_step_box(const Box& bx, const Par& par, const VMetric& vm, T* U, T* P, T* A, double dt,
+                                    int scheme, int p_current, double* max_rate) {
+  Geo G(bx);
+  const long N = 8 * G.ncell, NA = 3 * G.nvert;
+  ct_cell_field(bx, A, U);
+  long nfail = p_current ? 0 : con2prim_box(bx, par, vm, U, P, (int32_t*)nullptr);
+  std::vector<T> Un(U, U + N), An(A, A + NA), L(N), LA(NA);
+  if (scheme == 2) {  // classic RK4 (as rk4_step_box)
+    static const double a4[3] = {0.5, 0.5, 1.0};
+    static const double b4[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
+    std::vector<T> Acc(U, U + N), AccA(A, A + NA);
+    for (int s = 0; s < 4; ++s) {
+      if (s > 0) nfail += con2prim_box(bx, par, vm, U, P, (int32_t*)nullptr);
+      MagFlux<T> mf;
+      rhs_from_prims(bx, par, vm, P, L.data(), max_rate, &mf);
+      ct_edge_rhs(bx, mf, LA.data());
+      for (long x = 0; x < N; ++x) {
+        Acc[x] = Acc[x] + (b4[s] * dt) * L[x];
+        U[x] = (s < 3) ? Un[x] + (a4[s] * dt) * L[x] : Acc[x];
+      }
+      for (long x = 0; x < NA; ++x) {
+        AccA[x] = AccA[x] + (b4[s] * dt) * LA[x];
+        A[x] = (s < 3) ? An[x] + (a4[s] * dt) * LA[x] : AccA[x];
+      }
+      ct_cell_field(bx, A, U);
+    }
+  } else {
+    static const double c3[3] = {1.0, 0.25, 2.0 / 3.0};
+    static const double c2[2] = {1.0, 0.5};
+    const double* cs = scheme == 1 ? c2 : c3;
+    const int nst = scheme == 1 ? 2 : 3;
+    for (int s = 0; s < nst; ++s) {
+      if (s > 0) nfail += con2prim_box(bx, par, vm, U, P, (int32_t*)nullptr);
+      MagFlux<T> mf;
+      rhs_from_prims(bx, par, vm, P, L.data(), max_rate, &mf);
+      ct_edge_rhs(bx, mf, LA.data());
+      for (long x = 0; x < N; ++x) U[x] = Un[x] + cs[s] * ((U[x] - Un[x]) + dt * L[x]);
+      for (long x = 0; x < NA; ++x) A[x] = An[x] + cs[s] * ((A[x] - An[x]) + dt * LA[x]);
+      ct_cell_field(bx, A, U);
+    }
   }
   nfail += con2prim_box(bx, par, vm, U, P, (int32_t*)nullptr);
   return nfail;
@@ -1318,6 +1476,39 @@ int orc_point_nh_solve(const double* U, const double* g, const Par* par, double 
 }
 
 // Boundary fill of the 8 primitive fields of one box (ghost cells only).
+// Constrained transport: U's Bcal from A, and P's B = Bcal / sqrt(gamma) at the
+// cell centre (initial data).
+void orc_ct_init(const Box* bx, const double* alpha, const double* beta, const double* gamma, const double* A, double* U,
+                 double* P) {
+  Geo G(*bx);
+  VMetric vm = make_vm(*bx, alpha, beta, gamma);
+  ct_cell_field(*bx, A, U);
+  for (long k = 0; k < bx->n[2]; ++k)
+    for (long j = 0; j < bx->n[1]; ++j)
+      for (long i = 0; i < bx->n[0]; ++i) {
+        PMetric<double> m;
+        metric_centre(G, vm, i, j, k, m);
+        for (int d = 0; d < 3; ++d) P[(5 + d) * G.ncell + G.c(i, j, k)] = U[(5 + d) * G.ncell + G.c(i, j, k)] / m.sqrtg;
+      }
+}
+
+void orc_ct_face_field(const Box* bx, const double* A, double* Bf) { ct_face_field(*bx, A, Bf); }
+
+long orc_ct_step(const Box* bx, const Par* par, const double* alpha, const double* beta, const double* gamma, double* U,
+                 double* P, double* A, double dt, int scheme, int p_current, double* max_rate) {
+  return ct_step_box(*bx, *par, make_vm(*bx, alpha, beta, gamma), U, P, A, dt, scheme, p_current, max_rate);
+}
+
+// dA/dt from given primitives (their RHS's magnetic face fluxes).
+void orc_ct_edge_rhs(const Box* bx, const Par* par, const double* alpha, const double* beta, const double* gamma,
+                     double* P, double* dA) {
+  Geo G(*bx);
+  std::vector<double> L(8 * G.ncell);
+  MagFlux<double> mf;
+  rhs_from_prims(*bx, *par, make_vm(*bx, alpha, beta, gamma), P, L.data(), nullptr, &mf);
+  ct_edge_rhs(*bx, mf, dA);
+}
+
 void orc_fill_ghosts(const Box* bx, double* P) {
   Geo G(*bx);
   fill_ghosts(*bx, G, P);

@@ -371,3 +371,146 @@ def interior_mask(box: BoxSpec):
     g = box.ng
     m[g:g + box.n[2], g:g + box.n[1], g:g + box.n[0]] = True
     return m
+
+
+# --------------------------------------------------------------------------
+# constrained transport (Sec. III B): the vector potential on cell edges
+# --------------------------------------------------------------------------
+#
+# A is (3, vert_stride): A_e of an edge along e is stored like a vertex field
+# with the cell index along e in place of that vertex index; its position has
+# the cell-centre coordinate along e and vertex coordinates along the others.
+
+def edge_coords(box: BoxSpec, e):
+    """Coordinates (X, Y, Z), each shaped like the box's vertex grid, of the edges along e."""
+    ax = []
+    for d in range(3):
+        i = np.arange(box.vdims[d], dtype=np.float64)
+        ax.append(box.x0[d] + (i - box.ng + (0.5 if d == e else 0.0)) * box.dx[d])
+    Z, Y, X = np.meshgrid(ax[2], ax[1], ax[0], indexing="ij")
+    return X, Y, Z
+
+
+def uniform_potential(box: BoxSpec, B):
+    """A = (B^y z, B^z x, B^x y) on the edges: curl A = (B^x, B^y, B^z) everywhere."""
+    Xx, Yx, Zx = edge_coords(box, 0)
+    Xy, Yy, Zy = edge_coords(box, 1)
+    Xz, Yz, Zz = edge_coords(box, 2)
+    return np.stack([B[1] * Zx, B[2] * Xy, B[0] * Yz])
+
+
+def _pool_edges(prob, per_box):
+    A = np.zeros((3, prob.vert_stride))
+    for b, bx in enumerate(prob.boxes):
+        v0 = prob.vert_off[b]
+        A[:, v0:v0 + bx.nvert] = per_box[b].reshape(3, -1)
+    return A
+
+
+def ct_random(n=(12, 10, 8), seed=SEED_BASE + 31, recon=RECON_WENO5, bc=BC_PERIODIC, curved=False, amp=0.05):
+    """Smooth random flat-space primitives (mild ranges, Gamma = 5/3) on the unit cube
+    with a smooth random potential: A_e = amp / (2 pi) * (Fourier field, wavenumbers up
+    to 4) plus the potential of a uniform field (0.3, -0.2, 0.25).  The primitives' B is replaced by
+    curl A / sqrt(gamma) through the oracle's or the library's CT initialisation.
+    curved: the conformally flat metric of the curved recipe around (0.5, 0.5, 0.5)."""
+    rng = np.random.default_rng(seed)
+    gam = 5.0 / 3.0
+    dx = tuple(1.0 / v for v in n)
+    box = BoxSpec(tuple(n), 3, (bc,) * 6, (0.0, 0.0, 0.0), dx)
+    X, Y, Z = cell_centres(box)
+    f = flat_fields(rng, X, Y, Z, gam, mild=True)
+    if curved:
+        shifted = BoxSpec(box.n, box.ng, box.bc, (-0.5 - 2.0, -0.5, -0.5), dx)
+        met = curved_metric(shifted)
+    else:
+        met = flat_metric(box)
+    par = Params(recon=recon, eos_gamma=gam)
+    prob = _assemble("ct_random", [box], par, [f], [met], 0.25 * min(dx), 1, seed)
+    A = uniform_potential(box, (0.3, -0.2, 0.25))
+    for e in range(3):
+        A[e] += amp / (2.0 * np.pi) * _fourier_field(rng, *edge_coords(box, e))
+    prob.A = _pool_edges(prob, [A])
+    return prob
+
+
+def rotor(n=400, nz=1, seed=SEED_BASE + 40):
+    """The relativistic magnetic rotor (Sec. IV C): [-0.5, 0.5]^2, a cylinder of radius
+    0.1 with rho = 10 rotating at Omega = 9.95 (v_max = 0.995) in rho = 1, p = 1 everywhere,
+    B = (1, 0, 0); Gamma = 5/3, minmod, HLLE, copy boundaries in x and y (periodic along
+    the cylinder axis, n_z cells), flat metric, dt = dx / 4 (CFL 0.25)."""
+    gam = 5.0 / 3.0
+    dx = 1.0 / n
+    box = BoxSpec((n, n, nz), 3, (BC_OUTFLOW,) * 4 + (BC_PERIODIC,) * 2, (-0.5, -0.5, -0.5 * nz * dx),
+                  (dx, dx, dx))
+    X, Y, Z = cell_centres(box)
+    r = np.sqrt(X * X + Y * Y)
+    inside = r < 0.1
+    omega = 9.95
+    rho = np.where(inside, 10.0, 1.0)
+    p = np.ones_like(X)
+    vx = np.where(inside, -omega * Y, 0.0)
+    vy = np.where(inside, omega * X, 0.0)
+    z = np.zeros_like(X)
+    eps = p / ((gam - 1.0) * rho)
+    f = [rho, vx, vy, z, eps, z.copy(), z.copy(), z.copy()]
+    par = Params(recon=RECON_MINMOD, eos_gamma=gam)
+    prob = _assemble("rotor", [box], par, [f], [flat_metric(box)], 0.25 * dx, 1, seed)
+    prob.A = _pool_edges(prob, [uniform_potential(box, (1.0, 0.0, 0.0))])
+    return prob
+
+
+def cylindrical_explosion(n=200, nz=1, seed=SEED_BASE + 41):
+    """The cylindrical explosion (Sec. IV B): [-6, 6]^2, rho and p equal to their inner
+    values for r <= 0.8 and their outer values for r >= 1, with log-linear profiles in
+    between (R29); rho 1e-2 / 1e-4, p 1 / 3e-5, v = 0, B = (0.1, 0, 0), Gamma = 4/3,
+    minmod, HLLE, copy boundaries, flat metric, dt = dx / 4."""
+    gam = 4.0 / 3.0
+    dx = 12.0 / n
+    box = BoxSpec((n, n, nz), 3, (BC_OUTFLOW,) * 4 + (BC_PERIODIC,) * 2, (-6.0, -6.0, -0.5 * nz * dx),
+                  (dx, dx, dx))
+    X, Y, Z = cell_centres(box)
+    r = np.sqrt(X * X + Y * Y)
+    r_in, r_out = 0.8, 1.0
+
+    def profile(q_in, q_out):
+        t = np.clip((r - r_in) / (r_out - r_in), 0.0, 1.0)
+        return np.exp((1.0 - t) * np.log(q_in) + t * np.log(q_out))
+
+    rho = profile(1e-2, 1e-4)
+    p = profile(1.0, 3e-5)
+    z = np.zeros_like(X)
+    eps = p / ((gam - 1.0) * rho)
+    f = [rho, z, z.copy(), z.copy(), eps, z.copy(), z.copy(), z.copy()]
+    par = Params(recon=RECON_MINMOD, eos_gamma=gam)
+    prob = _assemble("explosion", [box], par, [f], [flat_metric(box)], 0.25 * dx, 1, seed)
+    prob.A = _pool_edges(prob, [uniform_potential(box, (0.1, 0.0, 0.0))])
+    return prob
+
+
+def field_loop(n=32, seed=SEED_BASE + 42, A0=1e-3, R=0.3, v=(0.5, 0.25)):
+    """Field-loop advection on the periodic unit square (flat space, Gamma = 5/3, rho = 1,
+    p = 1, uniform v, weak loop A_z = A0 (R - r) for r < R around (0.5, 0.5)): an exact
+    solution that translates with v, minmod + HLLE, dt = dx / 4."""
+    gam = 5.0 / 3.0
+    dx = 1.0 / n
+    box = BoxSpec((n, n, 1), 3, (BC_PERIODIC,) * 6, (0.0, 0.0, -0.5 * dx), (dx, dx, dx))
+    X, Y, Z = cell_centres(box)
+    one = np.ones_like(X)
+    z = np.zeros_like(X)
+    f = [one, v[0] * one, v[1] * one, z, one / (gam - 1.0), z.copy(), z.copy(), z.copy()]
+    par = Params(recon=RECON_MINMOD, eos_gamma=gam)
+    prob = _assemble("field_loop", [box], par, [f], [flat_metric(box)], 0.25 * dx, 1, seed)
+    prob.A = _pool_edges(prob, [field_loop_potential(box, 0.0, A0, R, v)])
+    return prob
+
+
+def field_loop_potential(box: BoxSpec, t, A0=1e-3, R=0.3, v=(0.5, 0.25)):
+    """The loop's potential translated by v t (periodic images on the unit square)."""
+    A = np.zeros((3,) + tuple(reversed(box.vdims)))
+    X, Y, _ = edge_coords(box, 2)
+    dxp = (X - 0.5 - v[0] * t + 0.5) % 1.0 - 0.5
+    dyp = (Y - 0.5 - v[1] * t + 0.5) % 1.0 - 0.5
+    r = np.sqrt(dxp * dxp + dyp * dyp)
+    A[2] = np.where(r < R, A0 * (R - r), 0.0)
+    return A
+
