@@ -230,6 +230,46 @@ int grmhd_rk_step_adjoint(const grmhd_domain* dom, const grmhd_params* par, cons
                           const double* stage_ckpt, double* P, double dt, int32_t scheme, const double* gU_out,
                           double* gU_in, void* ws, size_t ws_bytes, void* stream);
 
+/* ---- constrained transport (Sec. III B: the vector potential on cell edges) ----
+ *
+ * A: 3 fields (A_x, A_y, A_z), each vert_stride apart and laid out like the
+ * vertex metric.  A_e of the edge along axis e at cell index c_e along e and
+ * vertex indices along the two other axes sits at the vertex storage index
+ * with c_e in place of that vertex index.  Edges of the interior (cell index
+ * 0..n-1 along e, vertex index 0..n along the others) are read and written.
+ * The face field is Bcal = curl A (Bcal^d = d_a A_b - d_b A_a, (d, a, b)
+ * cyclic, one-sided differences across the face), whose discrete divergence
+ * vanishes to round-off; the cell-centred Bcal of U is the mean of the two
+ * face values.  The induction equation becomes d_t A_e = F^a(Bcal^b) =
+ * -F^b(Bcal^a), each taken as the mean of the HLLE fluxes of the two faces
+ * beside the edge (ghost columns have the fluxes of the columns they copy), the
+ * edge value the mean of the two.  The gauge term of A, a gradient that curl
+ * removes, is left out. */
+
+/* Initial data: P's B = (cell-centred curl A) / sqrt(gamma) on interior cells
+ * (P's other fields are kept), then U from P as grmhd_prim2con does. */
+int grmhd_ct_init(const grmhd_domain* dom, const grmhd_params* par, const grmhd_metric* met, const double* A,
+                  double* U, double* P, void* stream);
+
+/* Face field curl A on every interior face: 3 fields laid out like cells; the
+ * d-face at vertex index m along d sits at cell index m (m = n in the first
+ * ghost layer).  Other entries are not written. */
+int grmhd_ct_face_field(const grmhd_domain* dom, const double* A, double* Bface, void* stream);
+
+/* One method-of-lines step (SSPRK3, SSPRK2 or classic RK4) with constrained
+ * transport: U's Bcal is set from A^n, con2prim (skipped with p_current = 1),
+ * then per stage the stage kernel (its magnetic face fluxes kept), the same
+ * stage combine for A from the edge averages, and U_{s+1}'s Bcal from
+ * A_{s+1} before its con2prim.  U, P, A are updated in place.  max_rate,
+ * n_fail as grmhd_rk_step.  ws: grmhd_ct_workspace_bytes() bytes.  No stage
+ * checkpoints or adjoint. */
+int grmhd_rk_step_ct(const grmhd_domain* dom, const grmhd_params* par, const grmhd_metric* met, double* U, double* P,
+                     double* A, double dt, int32_t scheme, double* max_rate, int64_t* n_fail, void* ws,
+                     size_t ws_bytes, void* stream);
+
+/* Workspace bytes for grmhd_rk_step_ct. */
+size_t grmhd_ct_workspace_bytes(const grmhd_domain* dom, const grmhd_params* par, int32_t scheme);
+
 /* Workspace bytes for grmhd_rk_step (for_adjoint = 0) or
  * grmhd_rk_step_adjoint (for_adjoint = 1). */
 size_t grmhd_workspace_bytes(const grmhd_domain* dom, const grmhd_params* par, int32_t scheme,

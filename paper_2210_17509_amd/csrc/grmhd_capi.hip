@@ -555,6 +555,188 @@ __global__ __launch_bounds__(C2P_BLOCK) void k_fill(Table tab, double* X, int64_
   for (int q = 0; q < 8; ++q) X[q * cs + cc] = val;
 }
 
+// ---------------------------------------------------------------- constrained transport (Sec. III B)
+//
+// The vector potential A (3 fields, stored like the vertex metric) lives on cell
+// edges: A_e of the edge along e at cell index c_e and vertex indices along the
+// two other axes sits at the vertex-shaped index with c_e in place of that vertex
+// index.  The face field is Bcal = curl A, the cell's Bcal the mean of its two
+// face values; d_t A_e = F^a(Bcal^b) = -F^b(Bcal^a) (a = e+1, b = e+2 cyclic),
+// each the mean of the HLLE fluxes of the two faces beside the edge, and the
+// edge value the mean of the two.  The gauge term of A is a gradient, which curl
+// removes: it is left out.
+
+// Interior vertex point (n + 1 per axis) of workgroup blk, thread tid.
+__device__ __forceinline__ bool vert_point_of(const Table& tab, int blk, int tid, int& b, int p[3]) {
+  b = find_box(tab.vert_prefix, tab.nbox, blk);
+  const KBox& bx = tab.box[b];
+  const int lin = (blk - tab.vert_prefix[b]) * C2P_BLOCK + tid;
+  const int nx = bx.n[0] + 1, nxy = nx * (bx.n[1] + 1);
+  if (lin >= nxy * (bx.n[2] + 1)) return false;
+  p[2] = lin / nxy;
+  const int r = lin - p[2] * nxy;
+  p[1] = r / nx;
+  p[0] = r - p[1] * nx;
+  return true;
+}
+
+// box-local storage index of an interior-coordinate point on the vertex / cell grids
+__device__ __forceinline__ int64_t vpos(const KBox& bx, const int p[3]) {
+  return ((int64_t)(p[2] + bx.ng) * (bx.VXY / bx.VX) + (p[1] + bx.ng)) * bx.VX + (p[0] + bx.ng);
+}
+__device__ __forceinline__ int64_t cpos(const KBox& bx, const int p[3]) {
+  return ((int64_t)(p[2] + bx.ng) * (bx.NXY / bx.NX) + (p[1] + bx.ng)) * bx.NX + (p[0] + bx.ng);
+}
+// cell coordinate c (-1 <= c <= n) along an axis mapped into the box: the fluxes
+// of a ghost column are those of the column it copies
+__device__ __forceinline__ int col_map(const KBox& bx, int axis, int c) {
+  return c < 0 ? bx.mlo[axis][c + 3] : (c >= bx.n[axis] ? bx.mhi[axis][c - bx.n[axis]] : c);
+}
+
+// Face field Bcal^d of the d-face at vertex index p[d] along d (cells p[a], p[b]).
+__device__ __forceinline__ double face_curl(const KBox& bx, const double* __restrict__ A, int64_t vs, int d,
+                                            const int p[3]) {
+  const int a = (d + 1) % 3, b = (d + 2) % 3;
+  int pa[3] = {p[0], p[1], p[2]}, pb[3] = {p[0], p[1], p[2]};
+  ++pa[a];
+  ++pb[b];
+  const double dAb = A[b * vs + vpos(bx, pa)] - A[b * vs + vpos(bx, p)];
+  const double dAa = A[a * vs + vpos(bx, pb)] - A[a * vs + vpos(bx, p)];
+  return dAb * bx.inv_dx[a] - dAa * bx.inv_dx[b];
+}
+
+struct CTEdgeArgs {
+  Table tab;
+  const double* __restrict__ bflux;  // the stage kernel's transverse magnetic face fluxes (6 fields)
+  const double* An;                  // A^n
+  const double* As;                  // the stage state's potential
+  double* Aout;                      // SSPRK: A_{s+1}; RK4: the next stage state, or A^{n+1}
+  double* Acc;                       // RK4 accumulator
+  int64_t cs, vs;
+  double c, dt;                      // SSPRK: A_{s+1} = A^n + c ((A_s - A^n) + dt dA/dt)
+  double adt, bdt;                   // RK4: next = A^n + a dt dA/dt, Acc += b dt dA/dt
+  int32_t rk4, first, last;
+};
+
+__global__ __launch_bounds__(C2P_BLOCK) void k_ct_edge(CTEdgeArgs a) {
+  int b, p[3];
+  if (!vert_point_of(a.tab, blockIdx.x, threadIdx.x, b, p)) return;
+  const KBox& bx = a.tab.box[b];
+  const double* bf = a.bflux + bx.cell_off;
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    if (p[e] >= bx.n[e]) continue;  // an edge along e has a cell index along e
+    const int ea = (e + 1) % 3, eb = (e + 2) % 3;
+    double fa = 0.0, fb = 0.0;
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      int c1[3] = {p[0], p[1], p[2]}, c2[3] = {p[0], p[1], p[2]};
+      c1[eb] = col_map(bx, eb, p[eb] - 1 + side);  // a-faces beside the edge: F^a(Bcal^b)
+      c2[ea] = col_map(bx, ea, p[ea] - 1 + side);  // b-faces beside the edge: F^b(Bcal^a)
+      fa += bf[(2 * ea) * a.cs + cpos(bx, c1)];
+      fb += bf[(2 * eb + 1) * a.cs + cpos(bx, c2)];
+    }
+    const double E = 0.5 * (0.5 * fa - 0.5 * fb);
+    const int64_t x = e * a.vs + bx.vert_off + vpos(bx, p);
+    const double an = a.An[x];
+    if (!a.rk4) {
+      a.Aout[x] = an + a.c * ((a.As[x] - an) + a.dt * E);
+    } else {
+      const double acc = (a.first ? an : a.Acc[x]) + a.bdt * E;
+      if (a.last) {
+        a.Aout[x] = acc;
+      } else {
+        a.Acc[x] = acc;
+        a.Aout[x] = an + a.adt * E;
+      }
+    }
+  }
+}
+
+struct CTCellArgs {
+  Table tab;
+  const double* __restrict__ A;
+  double* U;
+  double* P;
+  const double* __restrict__ gamma;
+  int64_t cs, vs;
+  KPhys ph;
+  int32_t mode;  // 0: U's Bcal from A, then con2prim; 1: U's Bcal only; 2: P's B = Bcal / sqrt(gamma), U = P->U
+  unsigned long long* n_fail;
+};
+
+__global__ __launch_bounds__(C2P_BLOCK) void k_ct_cell(CTCellArgs a) {
+  int b, c, vb;
+  unsigned long long fail = 0;
+  if (cell_of(a.tab, blockIdx.x, threadIdx.x, b, c, vb)) {
+    const KBox& bx = a.tab.box[b];
+    const double* Ab = a.A + bx.vert_off;
+    const int ng = bx.ng;
+    const int k = c / bx.NXY - ng, j = (c / bx.NX) % (bx.NXY / bx.NX) - ng, i = c % bx.NX - ng;
+    double Bc[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      int lo[3] = {i, j, k}, hi[3] = {i, j, k};
+      ++hi[d];
+      Bc[d] = 0.5 * (face_curl(bx, Ab, a.vs, d, lo) + face_curl(bx, Ab, a.vs, d, hi));
+    }
+    const int64_t cc = bx.cell_off + c;
+    if (a.mode == 1) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) a.U[(5 + d) * a.cs + cc] = Bc[d];
+    } else {
+      CentreMetric cm;
+      centre_metric<false, false>(GlobalVerts{nullptr, nullptr, a.gamma + bx.vert_off, a.vs}, vb, bx.VX, bx.VXY, cm);
+      double U[8], P[8];
+      if (a.mode == 2) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) P[q] = a.P[q * a.cs + cc];
+        const double is = 1.0 / cm.sqrtg;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) P[5 + d] = Bc[d] * is;
+        p2c_cell(cm.g, cm.sqrtg, a.ph.gm1, P, U);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          a.P[q * a.cs + cc] = P[q];
+          a.U[q * a.cs + cc] = U[q];
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          U[q] = (q >= 5) ? Bc[q - 5] : a.U[q * a.cs + cc];
+          P[q] = a.P[q * a.cs + cc];
+        }
+        const int st = c2p_cell(cm.g, cm.gi, cm.sqrtg, a.ph, U, P);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          a.P[q * a.cs + cc] = P[q];
+          a.U[q * a.cs + cc] = U[q];
+        }
+        fail = (st >= C2P_NOCONV && st <= C2P_NONFINITE) ? 1ull : 0ull;
+      }
+    }
+  }
+  if (a.n_fail) {
+    for (int o = 32; o > 0; o >>= 1) fail += __shfl_xor(fail, o, 64);
+    if ((threadIdx.x & 63) == 0 && fail) atomicAdd(a.n_fail, fail);
+  }
+}
+
+// Face field curl A on every interior face, 3 cell-shaped fields (the d-face at
+// vertex index m along d at the cell index m).
+__global__ __launch_bounds__(C2P_BLOCK) void k_ct_face(Table tab, const double* __restrict__ A, double* Bf, int64_t cs,
+                                                       int64_t vs) {
+  int b, p[3];
+  if (!vert_point_of(tab, blockIdx.x, threadIdx.x, b, p)) return;
+  const KBox& bx = tab.box[b];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int ea = (d + 1) % 3, eb = (d + 2) % 3;
+    if (p[ea] >= bx.n[ea] || p[eb] >= bx.n[eb]) continue;
+    Bf[d * cs + bx.cell_off + cpos(bx, p)] = face_curl(bx, A + bx.vert_off, vs, d, p);
+  }
+}
+
 // ---------------------------------------------------------------- host side
 
 thread_local std::string g_last_error;
@@ -618,6 +800,7 @@ struct Prepared {
   int64_t c2p_blocks;
   int64_t tiles[NTILE];
   int64_t face_blocks[3];
+  int64_t vert_blocks;
 };
 std::mutex g_mu;
 std::unordered_map<const void*, Prepared> g_prepared;
@@ -649,7 +832,7 @@ int invalid(const char* why) {
 }
 
 size_t table_bytes(int32_t nbox) {
-  return sizeof(TableHeader) + sizeof(KBox) * (size_t)nbox + sizeof(int32_t) * (size_t)(nbox + 1) * (1 + NTILE + 3);
+  return sizeof(TableHeader) + sizeof(KBox) * (size_t)nbox + sizeof(int32_t) * (size_t)(nbox + 1) * (1 + NTILE + 3 + 1);
 }
 
 int periodic_map(int m, int n) { return ((m % n) + n) % n; }
@@ -749,6 +932,7 @@ Table make_table(const grmhd_domain* dom) {
   t.c2p_prefix = reinterpret_cast<const int32_t*>(base + sizeof(TableHeader) + sizeof(KBox) * (size_t)dom->nbox);
   t.tile_prefix = t.c2p_prefix + (dom->nbox + 1);
   t.face_prefix = t.tile_prefix + NTILE * (dom->nbox + 1);
+  t.vert_prefix = t.face_prefix + 3 * (dom->nbox + 1);
   t.nbox = dom->nbox;
   return t;
 }
@@ -833,6 +1017,7 @@ StageArgs stage_args(const grmhd_domain* dom, const grmhd_params* par, const KPh
   a.ckpt = nullptr;
   a.ckpt_in = nullptr;
   a.n_fail = nullptr;
+  a.bflux = nullptr;
   return a;
 }
 
@@ -911,8 +1096,9 @@ int grmhd_domain_prepare(const grmhd_domain* dom, void* stream) {
   int32_t* c2p = reinterpret_cast<int32_t*>(buf.data() + sizeof(TableHeader) + sizeof(KBox) * nb);
   int32_t* tp = c2p + (nb + 1);
   int32_t* fp = tp + NTILE * (nb + 1);
+  int32_t* vp = fp + 3 * (nb + 1);
   Prepared pr;
-  int64_t acc_c2p = 0, acc_t[NTILE] = {}, acc_f[3] = {0, 0, 0};
+  int64_t acc_c2p = 0, acc_t[NTILE] = {}, acc_f[3] = {0, 0, 0}, acc_v = 0;
   for (int b = 0; b < nb; ++b) {
     const grmhd_box& x = dom->box[b];
     KBox& k = kb[b];
@@ -947,7 +1133,13 @@ int grmhd_domain_prepare(const grmhd_domain* dom, void* stream) {
       const int64_t nf = int64_t(x.n[0] + (d == 0)) * (x.n[1] + (d == 1)) * (x.n[2] + (d == 2));
       acc_f[d] += (nf + FACE_BLOCK - 1) / FACE_BLOCK;
     }
+    vp[b] = (int32_t)acc_v;
+    const int64_t nvp = int64_t(x.n[0] + 1) * (x.n[1] + 1) * (x.n[2] + 1);
+    acc_v += (nvp + C2P_BLOCK - 1) / C2P_BLOCK;
   }
+  if (acc_v >= (int64_t(1) << 31)) return invalid("too many vertices");
+  vp[nb] = (int32_t)acc_v;
+  h->vert_blocks = acc_v;
   if (acc_c2p >= (int64_t(1) << 31)) return invalid("too many cells");
   c2p[nb] = (int32_t)acc_c2p;
   for (int t = 0; t < NTILE; ++t) {
@@ -974,6 +1166,7 @@ int grmhd_domain_prepare(const grmhd_domain* dom, void* stream) {
   pr.c2p_blocks = acc_c2p;
   for (int t = 0; t < NTILE; ++t) pr.tiles[t] = acc_t[t];
   for (int d = 0; d < 3; ++d) pr.face_blocks[d] = acc_f[d];
+  pr.vert_blocks = acc_v;
   std::lock_guard<std::mutex> lk(g_mu);
   g_prepared[dom->table] = pr;
   return GRMHD_OK;
@@ -1270,6 +1463,160 @@ int grmhd_rk_step_adjoint(const grmhd_domain* dom, const grmhd_params* par, cons
     a.mode = 0;
     e = launch_adj_cell(a, pr, s);
     if (e != hipSuccess) return fail_hip(e, "k_adj_cell");
+  }
+  return GRMHD_OK;
+}
+
+// ---- constrained transport ----
+
+// Workspace of grmhd_rk_step_ct: U-sets (SSPRK: the stage state; RK4: stage state,
+// L, accumulator), 6 magnetic face-flux fields, A-sets (SSPRK: stage state; RK4:
+// stage state, accumulator).
+static void ct_layout(const grmhd_domain* dom, int32_t scheme, size_t& u_sets, size_t& a_sets, size_t& bytes) {
+  u_sets = (scheme == GRMHD_RK4) ? 3 : 1;
+  a_sets = (scheme == GRMHD_RK4) ? 2 : 1;
+  bytes = sizeof(double) * ((8 * u_sets + 6) * (size_t)dom->cell_stride + 3 * a_sets * (size_t)dom->vert_stride);
+}
+
+size_t grmhd_ct_workspace_bytes(const grmhd_domain* dom, const grmhd_params* par, int32_t scheme) {
+  (void)par;
+  if (!dom || dom->cell_stride < 1 || dom->vert_stride < 1) return 0;
+  size_t u, a, b;
+  ct_layout(dom, scheme, u, a, b);
+  return b;
+}
+
+static hipError_t launch_ct_cell(const grmhd_domain* dom, const Prepared& pr, const KPhys& ph, const grmhd_metric* met,
+                                 const double* A, double* U, double* P, int mode, int64_t* n_fail, hipStream_t s) {
+  CTCellArgs c;
+  c.tab = make_table(dom);
+  c.A = A;
+  c.U = U;
+  c.P = P;
+  c.gamma = met->gamma;
+  c.cs = dom->cell_stride;
+  c.vs = dom->vert_stride;
+  c.ph = ph;
+  c.mode = mode;
+  c.n_fail = reinterpret_cast<unsigned long long*>(n_fail);
+  TimeScope ts(1, s);
+  hipLaunchKernelGGL(k_ct_cell, dim3((unsigned)pr.c2p_blocks), dim3(C2P_BLOCK), 0, s, c);
+  return hipGetLastError();
+}
+
+int grmhd_ct_init(const grmhd_domain* dom, const grmhd_params* par, const grmhd_metric* met, const double* A, double* U,
+                  double* P, void* stream) {
+  Prepared pr;
+  KPhys ph;
+  int r;
+  if ((r = check_domain(dom, pr)) || (r = check_params(par, nullptr, ph)) || (r = check_metric(met, false))) return r;
+  if (!A || !U || !P) return invalid("null A, U or P");
+  hipError_t e = launch_ct_cell(dom, pr, ph, met, A, U, P, 2, nullptr, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? GRMHD_OK : fail_hip(e, "k_ct_cell");
+}
+
+int grmhd_ct_face_field(const grmhd_domain* dom, const double* A, double* Bface, void* stream) {
+  Prepared pr;
+  int r;
+  if ((r = check_domain(dom, pr))) return r;
+  if (!A || !Bface) return invalid("null A or Bface");
+  hipLaunchKernelGGL(k_ct_face, dim3((unsigned)pr.vert_blocks), dim3(C2P_BLOCK), 0, static_cast<hipStream_t>(stream),
+                     make_table(dom), A, Bface, dom->cell_stride, dom->vert_stride);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? GRMHD_OK : fail_hip(e, "k_ct_face");
+}
+
+int grmhd_rk_step_ct(const grmhd_domain* dom, const grmhd_params* par, const grmhd_metric* met, double* U, double* P,
+                     double* A, double dt, int32_t scheme, double* max_rate, int64_t* n_fail, void* ws,
+                     size_t ws_bytes, void* stream) {
+  Prepared pr;
+  KPhys ph;
+  int r;
+  if ((r = check_domain(dom, pr)) || (r = check_params(par, dom, ph)) || (r = check_metric(met, true))) return r;
+  if (!P || !U || !A) return invalid("null P, U or A");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return invalid("dt must be positive and finite");
+  if (scheme != GRMHD_SSPRK3 && scheme != GRMHD_SSPRK2 && scheme != GRMHD_RK4) return invalid("unknown time integrator");
+  if (!ws) return invalid("null workspace");
+  size_t u_sets, a_sets, need;
+  ct_layout(dom, scheme, u_sets, a_sets, need);
+  if (ws_bytes < need) {
+    g_last_error = "workspace too small";
+    return GRMHD_EWORKSPACE;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const size_t fsz = 8 * (size_t)dom->cell_stride;
+  double* W1 = static_cast<double*>(ws);             // stage state
+  double* WL = W1 + fsz;                             // RK4: L of the stage state
+  double* WA = WL + fsz;                             // RK4: accumulated step
+  double* BF = W1 + u_sets * fsz;                    // magnetic face fluxes
+  double* A1 = BF + 6 * (size_t)dom->cell_stride;    // the stage state's potential
+  double* AA = A1 + 3 * (size_t)dom->vert_stride;    // RK4: accumulated potential
+  const Table tab = make_table(dom);
+  // U^n's Bcal from A^n, then its primitives (unless P already holds them)
+  hipError_t e = launch_ct_cell(dom, pr, ph, met, A, U, P, par->p_current == 1 ? 1 : 0, n_fail, s);
+  if (e != hipSuccess) return fail_hip(e, "k_ct_cell");
+  CTEdgeArgs ea;
+  ea.tab = tab;
+  ea.bflux = BF;
+  ea.An = A;
+  ea.Acc = AA;
+  ea.cs = dom->cell_stride;
+  ea.vs = dom->vert_stride;
+  ea.dt = dt;
+  ea.rk4 = (scheme == GRMHD_RK4);
+  StageArgs a = stage_args(dom, par, ph, met, P);
+  a.max_rate = max_rate;
+  a.bflux = BF;
+  if (scheme == GRMHD_RK4) {
+    static const double a4[3] = {0.5, 0.5, 1.0};
+    static const double b4[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
+    a.mode = 0;
+    a.Uout = WL;
+    for (int st = 0; st < 4; ++st) {
+      const bool last = (st == 3);
+      e = launch_stage(a, par->recon, par->precision, pr.tiles[a.tile], s);
+      if (e != hipSuccess) return fail_hip(e, "k_stage");
+      hipLaunchKernelGGL(k_rk4_combine, dim3((unsigned)pr.c2p_blocks), dim3(C2P_BLOCK), 0, s, tab, U, WL, WA, W1,
+                         st < 3 ? a4[st] * dt : 0.0, b4[st] * dt, (int32_t)(st == 0), (int32_t)last, dom->cell_stride);
+      ea.As = nullptr;
+      ea.Aout = last ? A : A1;
+      ea.adt = st < 3 ? a4[st] * dt : 0.0;
+      ea.bdt = b4[st] * dt;
+      ea.first = (st == 0);
+      ea.last = last;
+      ea.c = 0.0;
+      hipLaunchKernelGGL(k_ct_edge, dim3((unsigned)pr.vert_blocks), dim3(C2P_BLOCK), 0, s, ea);
+      e = hipGetLastError();
+      if (e != hipSuccess) return fail_hip(e, "k_ct_edge");
+      e = launch_ct_cell(dom, pr, ph, met, last ? A : A1, last ? U : W1, P, 0, n_fail, s);
+      if (e != hipSuccess) return fail_hip(e, "k_ct_cell");
+    }
+    return GRMHD_OK;
+  }
+  static const double c3[3] = {1.0, 0.25, 2.0 / 3.0};
+  static const double c2[2] = {1.0, 0.5};
+  const double* cst = scheme == GRMHD_SSPRK2 ? c2 : c3;
+  const int nst = scheme == GRMHD_SSPRK2 ? 2 : 3;
+  a.mode = 1;
+  a.dt = dt;
+  a.Un = U;
+  for (int st = 0; st < nst; ++st) {
+    const bool last = (st == nst - 1);
+    a.Us = (st == 0) ? U : W1;
+    a.Uout = last ? U : W1;
+    a.cstage = cst[st];
+    e = launch_stage(a, par->recon, par->precision, pr.tiles[a.tile], s);
+    if (e != hipSuccess) return fail_hip(e, "k_stage");
+    ea.As = (st == 0) ? A : A1;
+    ea.Aout = last ? A : A1;
+    ea.c = cst[st];
+    ea.first = ea.last = 0;
+    ea.adt = ea.bdt = 0.0;
+    hipLaunchKernelGGL(k_ct_edge, dim3((unsigned)pr.vert_blocks), dim3(C2P_BLOCK), 0, s, ea);
+    e = hipGetLastError();
+    if (e != hipSuccess) return fail_hip(e, "k_ct_edge");
+    e = launch_ct_cell(dom, pr, ph, met, last ? A : A1, last ? U : W1, P, 0, n_fail, s);
+    if (e != hipSuccess) return fail_hip(e, "k_ct_cell");
   }
   return GRMHD_OK;
 }

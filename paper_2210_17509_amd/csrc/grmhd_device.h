@@ -42,15 +42,17 @@ struct TableHeader {
   int64_t c2p_blocks;
   int64_t tiles[NTILE];
   int64_t face_blocks[3];
+  int64_t vert_blocks;
 };
 
 // Device table: header | KBox[nbox] | int32 c2p_prefix[nbox+1] | int32 tile_prefix[NTILE][nbox+1]
-//               | int32 face_prefix[3][nbox+1]
+//               | int32 face_prefix[3][nbox+1] | int32 vert_prefix[nbox+1]
 struct Table {
   const KBox* box;
   const int32_t* c2p_prefix;
   const int32_t* tile_prefix;  // [NTILE][nbox+1]
   const int32_t* face_prefix;  // [3][nbox+1], blocks of FACE_BLOCK faces per direction
+  const int32_t* vert_prefix;  // blocks of C2P_BLOCK interior vertex points (n+1 per axis)
   int32_t nbox;
 };
 

@@ -58,6 +58,10 @@ struct StageArgs {
   double* ckpt;
   double* ckpt_in;  // nullable: receives the stage's input primitives (P) of each cell
   unsigned long long* n_fail;
+  // nullable (constrained transport): the two transverse magnetic fluxes of every
+  // face, field 2 D + t (t = 0: Bcal^{(D+1)%3}, t = 1: Bcal^{(D+2)%3}) at the storage
+  // index of the face's cell (its high neighbour along D)
+  double* bflux;
 };
 
 __device__ __forceinline__ void block_max_atomic(double v, double* target) {
@@ -222,6 +226,13 @@ __device__ __forceinline__ void direction_phase(const StageArgs& a, const KBox& 
       const int slot = fl[0] + SX * (fl[1] + SY * fl[2]);
 #pragma unroll
       for (int q = 0; q < 8; ++q) sF[q][slot] = F[q];
+      if (a.bflux) {
+        const int ng = bx.ng;
+        const uint32_t c = ((org[2] + fl[2] + ng) * (bx.NXY / bx.NX) + (org[1] + fl[1] + ng)) * bx.NX + (org[0] + fl[0] + ng);
+        double* bf = a.bflux + bx.cell_off;
+        stg(bf + (2 * D) * a.cs, c, F[5 + (D + 1) % 3]);
+        stg(bf + (2 * D + 1) * a.cs, c, F[5 + (D + 2) % 3]);
+      }
     }
   }
   __syncthreads();

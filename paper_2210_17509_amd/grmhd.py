@@ -62,6 +62,12 @@ _lib.grmhd_rhs.argtypes = [_pd, _pp, _pm, _P, _P, _P, _P, _P, _P]
 _lib.grmhd_rk_step.argtypes = [_pd, _pp, _pm, _P, _P, ctypes.c_double, ctypes.c_int32, _P, _P, _P, _P,
                                ctypes.c_size_t, _P]
 _lib.grmhd_rk_step_noalloc.argtypes = [_pd, _pp, _pm, _P, _P, ctypes.c_double, ctypes.c_int32, _P, _P, _P, _P]
+_lib.grmhd_ct_init.argtypes = [_pd, _pp, _pm, _P, _P, _P, _P]
+_lib.grmhd_ct_face_field.argtypes = [_pd, _P, _P, _P]
+_lib.grmhd_rk_step_ct.argtypes = [_pd, _pp, _pm, _P, _P, _P, ctypes.c_double, ctypes.c_int32, _P, _P, _P,
+                                  ctypes.c_size_t, _P]
+_lib.grmhd_ct_workspace_bytes.argtypes = [_pd, _pp, ctypes.c_int32]
+_lib.grmhd_ct_workspace_bytes.restype = ctypes.c_size_t
 _lib.grmhd_workspace_bytes.argtypes = [_pd, _pp, ctypes.c_int32, ctypes.c_int32]
 _lib.grmhd_workspace_bytes.restype = ctypes.c_size_t
 _lib.grmhd_strerror.argtypes = [ctypes.c_int]
@@ -75,7 +81,8 @@ _lib.grmhd_timing_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINT
 
 EXPORTED = ["grmhd_domain_table_bytes", "grmhd_domain_prepare", "grmhd_prim2con", "grmhd_con2prim", "grmhd_rhs",
             "grmhd_rk_step", "grmhd_workspace_bytes", "grmhd_strerror", "grmhd_last_error", "grmhd_timing_enable",
-            "grmhd_timing_read", "grmhd_con2prim_adjoint", "grmhd_rk_step_adjoint", "grmhd_rk_step_noalloc"]
+            "grmhd_timing_read", "grmhd_con2prim_adjoint", "grmhd_rk_step_adjoint", "grmhd_rk_step_noalloc",
+            "grmhd_ct_init", "grmhd_ct_face_field", "grmhd_rk_step_ct", "grmhd_ct_workspace_bytes"]
 
 GRMHD_NOALLOC_SCRATCH_BYTES = 256 << 20  # the fixed scratch of grmhd_rk_step_noalloc
 
@@ -255,3 +262,32 @@ def grmhd_rk_step_adjoint(dom, params, met, stage_ckpt, P, dt, gU_out, gU_in, sc
                                       ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(ws.numel() * ws.element_size()),
                                       _stream(stream)))
     return ws
+
+
+# ------------------------------------------------------------------ constrained transport
+
+def grmhd_ct_init(dom, params, met, A, U, P, stream=None):
+    _check(_lib.grmhd_ct_init(ctypes.byref(dom.c), ctypes.byref(_par(params)), ctypes.byref(met.c), _ptr(A), _ptr(U),
+                              _ptr(P), _stream(stream)))
+
+
+def grmhd_ct_face_field(dom, A, Bface, stream=None):
+    _check(_lib.grmhd_ct_face_field(ctypes.byref(dom.c), _ptr(A), _ptr(Bface), _stream(stream)))
+
+
+def grmhd_ct_workspace_bytes(dom, params, scheme=GRMHD_SSPRK3):
+    return int(_lib.grmhd_ct_workspace_bytes(ctypes.byref(dom.c), ctypes.byref(_par(params)), int(scheme)))
+
+
+def grmhd_rk_step_ct(dom, params, met, U, P, A, dt, scheme=GRMHD_SSPRK3, max_rate=None, n_fail=None, ws=None,
+                     stream=None):
+    pc = _par(params)
+    need = grmhd_ct_workspace_bytes(dom, pc, scheme)
+    if ws is None:
+        ws = torch.empty((need + 7) // 8, dtype=torch.float64, device=U.device)
+    _check(_lib.grmhd_rk_step_ct(ctypes.byref(dom.c), ctypes.byref(pc), ctypes.byref(met.c), _ptr(U), _ptr(P), _ptr(A),
+                                 float(dt), int(scheme), _ptr(max_rate), _ptr(n_fail, torch.int64),
+                                 ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(ws.numel() * ws.element_size()),
+                                 _stream(stream)))
+    return ws
+
