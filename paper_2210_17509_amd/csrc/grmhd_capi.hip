@@ -1567,6 +1567,7 @@ int grmhd_rk_step_ct(const grmhd_domain* dom, const grmhd_params* par, const grm
   StageArgs a = stage_args(dom, par, ph, met, P);
   a.max_rate = max_rate;
   a.bflux = BF;
+  a.tile = CT_TILE;
   if (scheme == GRMHD_RK4) {
     static const double a4[3] = {0.5, 0.5, 1.0};
     static const double b4[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};

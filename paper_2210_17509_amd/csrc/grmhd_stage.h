@@ -33,6 +33,7 @@ constexpr size_t QUEUE_BYTES = 256;  // per-XCD tile-queue counters at the end o
 constexpr int TILE_X[NTILE] = {16, 8, 64, 16};
 constexpr int TILE_Y[NTILE] = {4, 8, 2, 4};
 constexpr int TILE_Z[NTILE] = {4, 4, 2, 3};
+constexpr int CT_TILE = 3;  // the tile of stage launches that keep the magnetic face fluxes
 
 struct StageArgs {
   Table tab;
@@ -60,7 +61,8 @@ struct StageArgs {
   unsigned long long* n_fail;
   // nullable (constrained transport): the two transverse magnetic fluxes of every
   // face, field 2 D + t (t = 0: Bcal^{(D+1)%3}, t = 1: Bcal^{(D+2)%3}) at the storage
-  // index of the face's cell (its high neighbour along D)
+  // index of the face's cell (its high neighbour along D); non-null selects the
+  // CT_TILE grid launch (tile and schedule are ignored)
   double* bflux;
 };
 
@@ -187,7 +189,7 @@ template <int TX, int TY, int TZ> struct TileGeo {
   static constexpr int nvf(bool shift) { return shift ? 10 : 7; }
 };
 
-template <int D, int RECON, typename R, bool SHIFT, int TX, int TY, int TZ>
+template <int D, int RECON, typename R, bool SHIFT, int TX, int TY, int TZ, bool BF>
 __device__ __forceinline__ void direction_phase(const StageArgs& a, const KBox& bx, const double* __restrict__ Pb,
                                                 const double* sV, const int org[3], const int l[3], bool valid,
                                                 double (*sF)[TileGeo<TX, TY, TZ>::maxslots()], double acc[8],
@@ -226,7 +228,7 @@ __device__ __forceinline__ void direction_phase(const StageArgs& a, const KBox& 
       const int slot = fl[0] + SX * (fl[1] + SY * fl[2]);
 #pragma unroll
       for (int q = 0; q < 8; ++q) sF[q][slot] = F[q];
-      if (a.bflux) {
+      if constexpr (BF) {
         const int ng = bx.ng;
         const uint32_t c = ((org[2] + fl[2] + ng) * (bx.NXY / bx.NX) + (org[1] + fl[1] + ng)) * bx.NX + (org[0] + fl[0] + ng);
         double* bf = a.bflux + bx.cell_off;
@@ -246,7 +248,7 @@ __device__ __forceinline__ void direction_phase(const StageArgs& a, const KBox& 
   __syncthreads();
 }
 
-template <int RECON, typename R, bool SHIFT, int TI>
+template <int RECON, typename R, bool SHIFT, int TI, bool BF = false>
 __device__ __forceinline__ void stage_tile(const StageArgs& a, int tg,
                                            double (*sF)[TileGeo<TILE_X[TI], TILE_Y[TI], TILE_Z[TI]>::maxslots()],
                                            double* sV, double& rate, unsigned long long& fail) {
@@ -289,9 +291,9 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int tg,
   double acc[8];
 #pragma unroll
   for (int q = 0; q < 8; ++q) acc[q] = 0.0;
-  direction_phase<0, RECON, R, SHIFT, TX, TY, TZ>(a, bx, Pb, sV, org, l, valid, sF, acc, rate);
-  direction_phase<1, RECON, R, SHIFT, TX, TY, TZ>(a, bx, Pb, sV, org, l, valid, sF, acc, rate);
-  direction_phase<2, RECON, R, SHIFT, TX, TY, TZ>(a, bx, Pb, sV, org, l, valid, sF, acc, rate);
+  direction_phase<0, RECON, R, SHIFT, TX, TY, TZ, BF>(a, bx, Pb, sV, org, l, valid, sF, acc, rate);
+  direction_phase<1, RECON, R, SHIFT, TX, TY, TZ, BF>(a, bx, Pb, sV, org, l, valid, sF, acc, rate);
+  direction_phase<2, RECON, R, SHIFT, TX, TY, TZ, BF>(a, bx, Pb, sV, org, l, valid, sF, acc, rate);
   if (valid) {
     const int ng = bx.ng;
     const int c = ((k + ng) * (bx.NXY / bx.NX) + (j + ng)) * bx.NX + (i + ng);
@@ -349,14 +351,15 @@ template <typename R, bool SHIFT, int RECON> struct StageWaves {
 
 // One workgroup per tile.  Workgroups are dispatched round-robin over the 8
 // XCDs; each XCD gets a contiguous run of tiles so tiles sharing halos share an L2.
-template <int RECON, typename R, bool SHIFT, int TI>
+// BF: also store the transverse magnetic face fluxes (a.bflux, constrained transport).
+template <int RECON, typename R, bool SHIFT, int TI, bool BF = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(StageWaves<R, SHIFT, RECON>::value))) void k_stage(StageArgs a) {
   using G = TileGeo<TILE_X[TI], TILE_Y[TI], TILE_Z[TI]>;
   __shared__ double sF[8][G::maxslots()];
   __shared__ double sV[G::nvf(SHIFT) * G::NVB];
   double rate = 0.0;
   unsigned long long fail = 0;
-  stage_tile<RECON, R, SHIFT, TI>(a, xcd_tile(blockIdx.x, gridDim.x), sF, sV, rate, fail);
+  stage_tile<RECON, R, SHIFT, TI, BF>(a, xcd_tile(blockIdx.x, gridDim.x), sF, sV, rate, fail);
   if (a.max_rate) block_max_atomic(rate, a.max_rate);
   if (a.n_fail) wave_count_atomic(fail, a.n_fail);
 }
@@ -410,6 +413,10 @@ hipError_t launch_stage_t(const StageArgs& a, int64_t blocks, hipStream_t s) {
 
 template <int RECON, typename R, bool SHIFT>
 hipError_t launch_stage_r(const StageArgs& a, int64_t blocks, hipStream_t s) {
+  if (a.bflux) {  // constrained transport: the 16x4x3 tile, one workgroup per tile
+    hipLaunchKernelGGL((k_stage<RECON, R, SHIFT, CT_TILE, true>), dim3((unsigned)blocks), dim3(256), 0, s, a);
+    return hipGetLastError();
+  }
   switch (a.tile) {
     case 0: return launch_stage_t<RECON, R, SHIFT, 0>(a, blocks, s);
     case 1: return launch_stage_t<RECON, R, SHIFT, 1>(a, blocks, s);
