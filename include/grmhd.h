@@ -184,9 +184,11 @@ int grmhd_rhs(const grmhd_domain* dom, const grmhd_params* par, const grmhd_metr
  * n_fail as above, accumulated over all stages.  The con2prim of each stage
  * state runs inside the stage kernel; the primitives rotate between P and
  * copies in the workspace and end in P.  ws: grmhd_workspace_bytes() bytes
- * (two 8-field sets, three for SSPRK3 with p_current = 1 and for RK4, then 256
- * bytes of tile-queue counters).  RK4 runs con2prim as its own launch before
- * each stage (the stage kernel then only evaluates L) and once at the end. */
+ * (two 8-field sets, three for SSPRK3 with p_current = 1, four for RK4: its
+ * stage state, accumulator and two primitive buffers; then 256 bytes of
+ * tile-queue counters).  RK4 stages are fused the same way: each stage
+ * kernel accumulates the step, forms the next stage state and recovers its
+ * primitives. */
 int grmhd_rk_step(const grmhd_domain* dom, const grmhd_params* par, const grmhd_metric* met,
                   double* U, double* P, double dt, int32_t scheme, double* stage_ckpt,
                   double* max_rate, int64_t* n_fail, void* ws, size_t ws_bytes, void* stream);
@@ -197,9 +199,10 @@ int grmhd_rk_step(const grmhd_domain* dom, const grmhd_params* par, const grmhd_
  * that the library holds on every device it runs on, for the life of the
  * process, instead of the caller's ws.  The call itself allocates nothing.
  * Limit: grmhd_workspace_bytes(dom, par, scheme, 0) must not exceed
- * GRMHD_NOALLOC_SCRATCH_BYTES (256 MiB: about 1.39 M cells with ghosts for
- * SSPRK3 with p_current = 1 or RK4, 2.09 M otherwise, e.g. a 105^3 or a
- * 121^3 box with 3 ghost layers); larger domains get GRMHD_EWORKSPACE and
+ * GRMHD_NOALLOC_SCRATCH_BYTES (256 MiB: about 2.09 M cells with ghosts for
+ * SSPRK2/3 without p_current, 1.39 M for SSPRK3 with p_current = 1, 1.05 M
+ * for RK4, e.g. a 121^3, 105^3 or 95^3 box with 3 ghost layers); larger
+ * domains get GRMHD_EWORKSPACE and
  * nothing is enqueued.  All calls on one device share that device's array and
  * leave it dirty; the step writes every scratch value before reading it.
  * Calls that overlap on one device (concurrent streams or threads) race on the

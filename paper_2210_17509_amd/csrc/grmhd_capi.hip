@@ -1018,6 +1018,9 @@ StageArgs stage_args(const grmhd_domain* dom, const grmhd_params* par, const KPh
   a.ckpt_in = nullptr;
   a.n_fail = nullptr;
   a.bflux = nullptr;
+  a.Acc = nullptr;
+  a.adt = a.bdt = 0.0;
+  a.rk_first = a.rk_last = 0;
   return a;
 }
 
@@ -1218,7 +1221,7 @@ int grmhd_rhs(const grmhd_domain* dom, const grmhd_params* par, const grmhd_metr
 // buffer, plus a second primitive buffer when the step starts from the caller's
 // P with an odd number of stages (so the last stage can end in P).
 static size_t step_sets(const grmhd_params* par, int32_t scheme) {
-  if (scheme == GRMHD_RK4) return 3;  // stage state, L, accumulator
+  if (scheme == GRMHD_RK4) return 4;  // stage state, accumulator, two primitive buffers
   return (par && par->p_current == 1 && scheme == GRMHD_SSPRK3) ? 3 : 2;
 }
 
@@ -1228,9 +1231,11 @@ size_t grmhd_workspace_bytes(const grmhd_domain* dom, const grmhd_params* par, i
   return for_adjoint ? 2 * field : step_sets(par, scheme) * field + QUEUE_BYTES;
 }
 
-// Classic RK4 (Sec. IV A, Sec. V setupB): per stage, con2prim of the stage state
-// into P (skipped for U^n with p_current), the stage kernel evaluating L into
-// the workspace, then k_rk4_combine; con2prim of U^{n+1} at the end.
+// Classic RK4 (Sec. IV A, Sec. V setupB), fused like the SSPRK stages: con2prim
+// of U^n (skipped with p_current), then per stage the stage kernel evaluates L,
+// accumulates the step (Acc), forms the next stage state (or U^{n+1}) and
+// recovers its primitives in registers.  The primitives rotate P -> Pw -> Pw2
+// -> Pw -> P, so the step ends in the caller's P.
 static int rk4_step(const grmhd_domain* dom, const Prepared& pr, const KPhys& ph, const grmhd_params* par,
                     const grmhd_metric* met, double* U, double* P, double dt, double* max_rate, int64_t* n_fail,
                     void* ws, hipStream_t s) {
@@ -1238,34 +1243,38 @@ static int rk4_step(const grmhd_domain* dom, const Prepared& pr, const KPhys& ph
   static const double b4[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
   const size_t fsz = 8 * (size_t)dom->cell_stride;
   double* W1 = static_cast<double*>(ws);  // stage state
-  double* WL = W1 + fsz;                  // L of the stage state
-  double* WA = WL + fsz;                  // accumulated step
-  const Table tab = make_table(dom);
+  double* WA = W1 + fsz;                  // accumulated step
+  double* Pw = WA + fsz;                  // primitive buffers
+  double* Pw2 = Pw + fsz;
+  hipError_t e = hipSuccess;
+  if (par->p_current != 1) {
+    e = launch_c2p(dom, pr, ph, met, U, P, nullptr, nullptr, n_fail, s);
+    if (e != hipSuccess) return fail_hip(e, "k_con2prim");
+  }
   StageArgs a = stage_args(dom, par, ph, met, P);
-  a.mode = 0;
+  a.mode = 2;
   a.max_rate = max_rate;
-  a.Uout = WL;
+  a.n_fail = reinterpret_cast<unsigned long long*>(n_fail);
+  a.Un = U;
+  a.Acc = WA;
   if (par->schedule == GRMHD_SCHED_QUEUE) {
     a.queue = reinterpret_cast<unsigned int*>(static_cast<char*>(ws) + sizeof(double) * step_sets(par, GRMHD_RK4) * fsz);
     a.persist_blocks = persistent_blocks();
   }
-  hipError_t e = hipSuccess;
+  double* pin[4] = {P, Pw, Pw2, Pw};
+  double* pout[4] = {Pw, Pw2, Pw, P};
   for (int st = 0; st < 4; ++st) {
-    double* Us = (st == 0) ? U : W1;
-    if (st > 0 || par->p_current != 1) {
-      e = launch_c2p(dom, pr, ph, met, Us, P, nullptr, nullptr, n_fail, s);
-      if (e != hipSuccess) return fail_hip(e, "k_con2prim");
-    }
+    a.P = pin[st];
+    a.Pout = pout[st];
+    a.Uout = (st == 3) ? U : W1;
+    a.adt = st < 3 ? a4[st] * dt : 0.0;
+    a.bdt = b4[st] * dt;
+    a.rk_first = (st == 0);
+    a.rk_last = (st == 3);
     e = launch_stage(a, par->recon, par->precision, pr.tiles[a.tile], s);
     if (e != hipSuccess) return fail_hip(e, "k_stage");
-    hipLaunchKernelGGL(k_rk4_combine, dim3((unsigned)pr.c2p_blocks), dim3(C2P_BLOCK), 0, s, tab, U, WL, WA, W1,
-                       st < 3 ? a4[st] * dt : 0.0, b4[st] * dt, (int32_t)(st == 0), (int32_t)(st == 3),
-                       dom->cell_stride);
-    e = hipGetLastError();
-    if (e != hipSuccess) return fail_hip(e, "k_rk4_combine");
   }
-  e = launch_c2p(dom, pr, ph, met, U, P, nullptr, nullptr, n_fail, s);
-  return e == hipSuccess ? GRMHD_OK : fail_hip(e, "k_con2prim");
+  return GRMHD_OK;
 }
 
 // One step of grmhd_rk_step with the workspace ws (ws_bytes bytes).

@@ -47,7 +47,11 @@ struct StageArgs {
   const double* __restrict__ gamma;
   int64_t cs, vs;
   double cstage, dt;
-  int32_t mode;  // 0: Uout = dU/dt; 1: Uout = Un + c ((Us - Un) + dt dU/dt)
+  int32_t mode;  // 0: Uout = dU/dt; 1: Uout = Un + c ((Us - Un) + dt dU/dt); 2: classic RK4 stage
+  // mode 2: Acc = (rk_first ? Un : Acc) + bdt dU/dt; Uout = Un + adt dU/dt, or Acc after the last stage
+  double* Acc;
+  double adt, bdt;
+  int32_t rk_first, rk_last;
   KPhys ph;
   double* max_rate;
   unsigned int* queue;  // non-null: persistent launch over per-XCD tile queues
@@ -312,11 +316,28 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int tg,
       for (int q = 0; q < 8; ++q) stg(a.Uout + q * a.cs + bx.cell_off, (uint32_t)c, acc[q] + S[q]);
     } else {
       double u[8];
+      if (a.mode == 1) {
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const double un = ldg(a.Un + q * a.cs + bx.cell_off, (uint32_t)c);
-        const double us = ldg(a.Us + q * a.cs + bx.cell_off, (uint32_t)c);
-        u[q] = un + a.cstage * ((us - un) + a.dt * (acc[q] + S[q]));
+        for (int q = 0; q < 8; ++q) {
+          const double un = ldg(a.Un + q * a.cs + bx.cell_off, (uint32_t)c);
+          const double us = ldg(a.Us + q * a.cs + bx.cell_off, (uint32_t)c);
+          u[q] = un + a.cstage * ((us - un) + a.dt * (acc[q] + S[q]));
+        }
+      } else {
+        // classic RK4: the step's accumulator and the next stage state (or the step's end)
+        double ac[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const double un = ldg(a.Un + q * a.cs + bx.cell_off, (uint32_t)c);
+          const double prev = a.rk_first ? un : ldg(a.Acc + q * a.cs + bx.cell_off, (uint32_t)c);
+          const double L = acc[q] + S[q];
+          ac[q] = prev + a.bdt * L;
+          u[q] = a.rk_last ? ac[q] : un + a.adt * L;
+        }
+        if (!a.rk_last) {
+#pragma unroll
+          for (int q = 0; q < 8; ++q) stg(a.Acc + q * a.cs + bx.cell_off, (uint32_t)c, ac[q]);
+        }
       }
       if (a.ckpt_in) {  // after the loads above (a store ahead of them would hold them back)
 #pragma unroll
