@@ -181,8 +181,8 @@ def hbm_summary(args):
         "# FETCH_SIZE / WRITE_SIZE are KiB per dispatch; each is scaled by what the same counter",
         "# reads for a plain 1 GiB device copy (bench.py --calibrate-copy).",
         "# Commands (repository root, one MI355X):",
-        f"#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d F -o bench -- python bench.py --workload {args.workload} --steps 1 --warmup 0 --no-cpu-baseline --no-adjoint",
-        f"#   rocprofv3 --pmc WRITE_SIZE --output-format csv -d W -o bench -- python bench.py --workload {args.workload} --steps 1 --warmup 0 --no-cpu-baseline --no-adjoint",
+        f"#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d F -o bench -- python bench.py --workload {args.workload} --steps 1 --warmup 0 --no-cpu-baseline --no-adjoint --no-extras",
+        f"#   rocprofv3 --pmc WRITE_SIZE --output-format csv -d W -o bench -- python bench.py --workload {args.workload} --steps 1 --warmup 0 --no-cpu-baseline --no-adjoint --no-extras",
         "#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d CF -o copy -- python bench.py --calibrate-copy",
         "#   rocprofv3 --pmc WRITE_SIZE --output-format csv -d CW -o copy -- python bench.py --calibrate-copy",
         f"#   python bench.py --workload {args.workload} --hbm-summary F W CF CW",
@@ -241,7 +241,7 @@ def sq_summary(args):
             means[c] = sum(v for _, v in rows) / len(rows)
     waves = means["SQ_WAVES"]
     run = (f"--output-format csv -d {{}} -o bench -- python bench.py --workload {args.workload} --steps 1 "
-           "--warmup 0 --no-cpu-baseline --no-adjoint")
+           "--warmup 0 --no-cpu-baseline --no-adjoint --no-extras")
     lines = [f"# SQ counters of the stage kernel (con2prim included), workload: {WORKLOADS[args.workload]['desc']}",
              f"# (mean over the {ndisp} stage dispatches of one step; *_CYCLES and ACTIVE/WAIT counters in "
              "quad-cycles, summed over SEs)",
@@ -264,7 +264,7 @@ def sq_summary(args):
         lines.append(f"issued FP64 lane-flops per launch (64 x (ADD + MUL + TRANS + 2 FMA)): {lane_flops:.4e}"
                      f" = {lane_flops / alg:.2f} x the counted right-hand side ({alg:.4e}; con2prim and"
                      " masked lanes account for the rest)")
-        ms = _stats_avg_ms("k_stage<1, double, false, 3>")
+        ms = _stats_avg_ms("k_stage<1, double, false, 3, false>")
         if ms:
             lines.append(f"issued FP64 rate at the kernel-trace mean {ms:.4f} ms: {lane_flops / ms / 1e9:.1f} TFLOP/s"
                          f" = {lane_flops / ms / 1e9 / FP64_VECTOR_PEAK_TFLOPS:.3f} of the FP64 vector peak")
