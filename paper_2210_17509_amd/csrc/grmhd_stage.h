@@ -292,28 +292,39 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int tg,
     }
   }
   __syncthreads();
+  // The cell's source terms first (the centre metric, its derivatives and
+  // T^{mu nu}(P)), so that their temporaries are dead before the face phases; the
+  // flux differences are then added to them (the oracle's order of summation).
+  const int ng = bx.ng;
+  const int c = ((k + ng) * (bx.NXY / bx.NX) + (j + ng)) * bx.NX + (i + ng);
+  const uint32_t lv = l[0] + G::VBX * (l[1] + G::VBY * l[2]);
+  const LdsVerts<G::NVB> vt{sV};
   double acc[8];
 #pragma unroll
   for (int q = 0; q < 8; ++q) acc[q] = 0.0;
-  direction_phase<0, RECON, R, SHIFT, TX, TY, TZ, BF>(a, bx, Pb, sV, org, l, valid, sF, acc, rate);
-  direction_phase<1, RECON, R, SHIFT, TX, TY, TZ, BF>(a, bx, Pb, sV, org, l, valid, sF, acc, rate);
-  direction_phase<2, RECON, R, SHIFT, TX, TY, TZ, BF>(a, bx, Pb, sV, org, l, valid, sF, acc, rate);
   if (valid) {
-    const int ng = bx.ng;
-    const int c = ((k + ng) * (bx.NXY / bx.NX) + (j + ng)) * bx.NX + (i + ng);
-    const uint32_t lv = l[0] + G::VBX * (l[1] + G::VBY * l[2]);
-    const LdsVerts<G::NVB> vt{sV};
     CentreMetric cm;
     centre_metric<SHIFT, true>(vt, lv, G::VBX, G::VBX * G::VBY, cm);
     MetricDeriv md;
     metric_deriv<SHIFT>(vt, lv, G::VBX, G::VBX * G::VBY, bx.inv_dx, md);
-    double P[8], S[8];
+    double P[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) P[q] = ldg(Pb + q * a.cs, (uint32_t)c);
-    sources_T<SHIFT>(cm, md, P, a.ph.gam, S);
+    sources_T<SHIFT>(cm, md, P, a.ph.gam, acc);
+  }
+  direction_phase<0, RECON, R, SHIFT, TX, TY, TZ, BF>(a, bx, Pb, sV, org, l, valid, sF, acc, rate);
+  direction_phase<1, RECON, R, SHIFT, TX, TY, TZ, BF>(a, bx, Pb, sV, org, l, valid, sF, acc, rate);
+  direction_phase<2, RECON, R, SHIFT, TX, TY, TZ, BF>(a, bx, Pb, sV, org, l, valid, sF, acc, rate);
+  if (valid) {
+    // the spatial metric at the centre again, for con2prim
+    CentreMetric cm;
+    centre_metric<false, false>(vt, lv, G::VBX, G::VBX * G::VBY, cm);
+    double P[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) P[q] = ldg(Pb + q * a.cs, (uint32_t)c);
     if (a.mode == 0) {
 #pragma unroll
-      for (int q = 0; q < 8; ++q) stg(a.Uout + q * a.cs + bx.cell_off, (uint32_t)c, acc[q] + S[q]);
+      for (int q = 0; q < 8; ++q) stg(a.Uout + q * a.cs + bx.cell_off, (uint32_t)c, acc[q]);
     } else {
       double u[8];
       if (a.mode == 1) {
@@ -321,7 +332,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int tg,
         for (int q = 0; q < 8; ++q) {
           const double un = ldg(a.Un + q * a.cs + bx.cell_off, (uint32_t)c);
           const double us = ldg(a.Us + q * a.cs + bx.cell_off, (uint32_t)c);
-          u[q] = un + a.cstage * ((us - un) + a.dt * (acc[q] + S[q]));
+          u[q] = un + a.cstage * ((us - un) + a.dt * acc[q]);
         }
       } else {
         // classic RK4: the step's accumulator and the next stage state (or the step's end)
@@ -330,7 +341,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int tg,
         for (int q = 0; q < 8; ++q) {
           const double un = ldg(a.Un + q * a.cs + bx.cell_off, (uint32_t)c);
           const double prev = a.rk_first ? un : ldg(a.Acc + q * a.cs + bx.cell_off, (uint32_t)c);
-          const double L = acc[q] + S[q];
+          const double L = acc[q];
           ac[q] = prev + a.bdt * L;
           u[q] = a.rk_last ? ac[q] : un + a.adt * L;
         }
