@@ -354,7 +354,8 @@ __device__ __forceinline__ R weno5(R a, R b, R c, R d, R e, R eps, int zp) {
 // of the other) and two of their three second differences (those over cells
 // 1..3 and 2..4).  In FP64 one reciprocal serves both normalisations while
 // the product of the two denominators stays well inside the exponent range
-// (not for WENO-Z with p = 2, whose denominators can reach 1e-240).
+// (not for WENO-Z with p = 2, whose denominators can reach 1e-240); FP32 takes
+// one refined reciprocal per side.
 template <bool ZW, int ZPC = 0, typename R>
 __device__ __forceinline__ void weno5_lr(const R* s, R eps, int zp, R& PL, R& PR) {
   if (ZPC != 0) zp = ZPC;
@@ -376,14 +377,21 @@ __device__ __forceinline__ void weno5_lr(const R* s, R eps, int zp, R& PL, R& PR
   weno5_weights<ZW>(bR0, bR1, bR2, eps, zp, r0, r1, r2);
   const R nL = l0 * qa + l1 * qb + l2 * qc, dL = R(6) * (l0 + l1 + l2);
   const R nR = r0 * qd + r1 * qc + r2 * qb, dR = R(6) * (r0 + r1 + r2);
-  const R prod = dL * dR;
-  if (sizeof(R) == 8 && !(ZW && zp == 2) && prod > R(1e-300) && prod < R(1e300)) {
-    const R inv = rcp_r(prod);
-    PL = nL * (dR * inv);
-    PR = nR * (dL * inv);
+  if constexpr (sizeof(R) == 4) {
+    // FP32: a refined reciprocal per side (the product of the two denominators
+    // could leave the FP32 range)
+    PL = nL * rcp_r(dL);
+    PR = nR * rcp_r(dR);
   } else {
-    PL = nL / dL;
-    PR = nR / dR;
+    const R prod = dL * dR;
+    if (!(ZW && zp == 2) && prod > R(1e-300) && prod < R(1e300)) {
+      const R inv = rcp_r(prod);
+      PL = nL * (dR * inv);
+      PR = nR * (dL * inv);
+    } else {
+      PL = nL / dL;
+      PR = nR / dR;
+    }
   }
 }
 

@@ -146,9 +146,11 @@ __device__ __forceinline__ void face_flux(const StageArgs& a, const KBox& bx, co
       constexpr bool z = (RECON >= GRMHD_RECON_WENOZ);
       constexpr int zp = (RECON == RECON_WENOZ2) ? 2 : 1;
       const R eps = (R)(z ? a.ph.wenoz_eps : a.ph.weno_eps);
-      if constexpr (sizeof(R) == 8) {
+      if constexpr (sizeof(R) == 8 || !z) {
+        // both sides at once (shared candidates and smoothness terms)
         weno5_lr<z, zp>(s, eps, zp, PL[q], PR[q]);
       } else {
+        // FP32 WENO-Z keeps its per-weight ratios, side by side
         PL[q] = weno5<z, zp>(s[0], s[1], s[2], s[3], s[4], eps, zp);
         PR[q] = weno5<z, zp>(s[5], s[4], s[3], s[2], s[1], eps, zp);
       }
