@@ -471,6 +471,21 @@ def mixed_bench(args, steps=50):
     return out
 
 
+def setupA_bench(args, name="setupA240", steps=10):
+    """The stand-in for the paper's setupA (its own single-GPU comparison: static
+    spacetime, ideal gas, RK2): the curved recipe with periodic faces at 240^3,
+    SSPRK2, in the paper's unit of zone-cycles/s (full steps of every cell)."""
+    r = run_workload(name, args, steps=steps, warmup=2)
+    spec = WORKLOADS[name]
+    out = {"workload": spec["desc"], "zone_cycles_per_s": r["ncell"] * steps / r["wall"],
+           "zone_updates_per_s_per_stage": r["ncell"] * r["stages"] * steps / r["wall"], "steps": steps,
+           "n_fail": r["nfail"],
+           "paper_context": {"zone_cycles_per_s": spec["paper_v100"],
+                             "machine": "one Summit V100 (the paper's setupA, another machine: context only)"}}
+    del r
+    return out
+
+
 def field_errors(prob, a, b):
     """Per-field relative L-inf and L2 of a against b over interior cells (both (8, cells))."""
     import numpy as np
@@ -586,6 +601,7 @@ def main():
     if not args.no_extras and args.workload == "curved256":
         out["batched"] = batched_bench(args, value)
         out["mixed_precision"] = mixed_bench(args)
+        out["setupA_standin"] = setupA_bench(args)
     if not args.no_adjoint:
         a = adjoint_bench(args)
         out["adjoint_forward_ratio"] = a["value"]
