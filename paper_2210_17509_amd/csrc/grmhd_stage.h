@@ -109,6 +109,12 @@ hipError_t launch_stage_recon(const StageArgs& a, int precision, int64_t blocks,
 namespace gk {
 namespace {
 
+// Stencil prefetch distance of the face loop, in fields, for FP64 reconstruction.
+// One field ahead is 5% faster than none on the curved 256^3 step (two or three
+// ahead gain nothing more); with FP32 reconstruction the same prefetch is 5%
+// slower, so there the loads stay where they are used.
+constexpr int FACE_PF64 = 1;
+
 // Flux through the low face (direction D) of cell (i, j, k); the face's 4
 // vertices are read through vt at vb, vb + sa, vb + sb, vb + sa + sb.
 template <int D, int RECON, typename R, bool SHIFT, typename V>
@@ -132,13 +138,25 @@ __device__ __forceinline__ void face_flux(const StageArgs& a, const KBox& bx, co
     const int mm = (m < 0) ? bx.mlo[D][m + 3] : (m >= nD ? bx.mhi[D][m - nD] : m);
     idx[o] = (uint32_t)(base + mm * sD);
   }
+  // The stencils of the next PF fields are loaded while a field is being
+  // reconstructed, so that several fields' loads are in flight at once.
+  constexpr int PF = sizeof(R) == 8 ? FACE_PF64 : 0;
+  constexpr int NB = PF + 1;
+  double ring[NB][6];
+#pragma unroll
+  for (int p = 0; p < PF; ++p)
+#pragma unroll
+    for (int o = O0; o < O1; ++o) ring[p][o] = ldg(Pb + p * a.cs, idx[o]);
   R PL[8], PR[8];
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
-    const double* __restrict__ f = Pb + q * a.cs;
+    if (q + PF < 8) {
+#pragma unroll
+      for (int o = O0; o < O1; ++o) ring[(q + PF) % NB][o] = ldg(Pb + (q + PF) * a.cs, idx[o]);
+    }
     R s[6];
 #pragma unroll
-    for (int o = O0; o < O1; ++o) s[o] = (R)ldg(f, idx[o]);
+    for (int o = O0; o < O1; ++o) s[o] = (R)ring[q % NB][o];
     if (RECON == GRMHD_RECON_MINMOD) {
       PL[q] = s[2] + R(0.5) * minmod(s[2] - s[1], s[3] - s[2]);
       PR[q] = s[3] - R(0.5) * minmod(s[3] - s[2], s[4] - s[3]);
