@@ -76,7 +76,7 @@ enum { GRMHD_SCHED_GRID = 0, GRMHD_SCHED_QUEUE = 1 };
 /* per-cell con2prim status */
 enum {
   GRMHD_C2P_OK = 0,        /* 3D Newton-Raphson converged */
-  GRMHD_C2P_FLOOR = 1,     /* density below rho_atm: atmosphere applied */
+  GRMHD_C2P_FLOOR = 1,     /* density below rho_atm (1 + 1e-6): atmosphere applied */
   GRMHD_C2P_NOCONV = 2,    /* no method converged: atmosphere applied */
   GRMHD_C2P_UNPHYS = 3,    /* only unphysical roots found: atmosphere applied */
   GRMHD_C2P_NONFINITE = 4, /* non-finite conserved input: atmosphere applied */
@@ -157,8 +157,10 @@ int grmhd_prim2con(const grmhd_domain* dom, const grmhd_params* par, const grmhd
  * primitives already in P, falling back to the Newman-Hamlin pressure
  * iteration (then a Newton polish) when it fails.  P is the guess on input
  * and the result on output.  Cells that cannot be recovered, or whose density
- * is below rho_atm, are reset to the atmosphere (rho_atm, v = 0, p =
- * atm_K rho_atm^atm_gamma, B kept) and U is rewritten there.
+ * (D / sqrt(gamma) before, rho after a recovery) is below rho_atm (1 + 1e-6),
+ * are reset to the atmosphere (rho_atm, v = 0, p = atm_K rho_atm^atm_gamma,
+ * B kept) and U is rewritten there; a cell already at the atmosphere thus
+ * stays there with status FLOOR.
  * status: per storage cell int32 GRMHD_C2P_* (interior cells written), or NULL.
  * n_fail: device int64 incremented by the count of statuses 2-4, or NULL. */
 int grmhd_con2prim(const grmhd_domain* dom, const grmhd_params* par, const grmhd_metric* met,

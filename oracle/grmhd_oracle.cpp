@@ -602,7 +602,12 @@ template <class T> void sources_3p1(const PMetric<T>& m, const MetricDeriv& D, c
 
 enum { C2P_OK = 0, C2P_FLOOR = 1, C2P_NOCONV = 2, C2P_UNPHYS = 3, C2P_NONFINITE = 4, C2P_FALLBACK = 5 };
 
-struct AtmData { double rho, p; };
+// rho, p: the atmosphere state; floor: densities below it are the atmosphere.
+// The floor sits a relative 1e-6 above rho (a reading: the paper gives only the
+// atmosphere's values).  The atmosphere state itself in a strong field has its
+// thermal energy below the rounding of tau, so recovering it would succeed or
+// fail on the last bit of tau; at the floor it is recognised before any recovery.
+struct AtmData { double rho, p, floor; };
 
 // Atmosphere state (Sec. IV, TOV test): rho = rho_atm, v = 0, p from the
 // polytrope K rho^gamma_atm, eps = p / ((Gamma-1) rho), B kept; U rewritten.
@@ -790,7 +795,7 @@ template <class T> int con2prim_point(const PMetric<T>& m, const Par& par, const
   const double gf = gam / (gam - 1.0);
   C2PIn<T> c;
   c2p_inputs(m, U, c);
-  if (c.Dt < atm.rho) {
+  if (c.Dt < atm.floor) {
     atmosphere(m, par, atm, U, P);
     return C2P_FLOOR;
   }
@@ -833,7 +838,7 @@ template <class T> int con2prim_point(const PMetric<T>& m, const Par& par, const
     atmosphere(m, par, atm, U, P);
     return st;
   }
-  if (Pn[0] < atm.rho) {
+  if (Pn[0] < atm.floor) {
     atmosphere(m, par, atm, U, P);
     return C2P_FLOOR;
   }
@@ -970,6 +975,7 @@ template <class T> void fill_ghosts(const Box& bx, const Geo& G, T* P) {
 static AtmData atm_of(const Par& par) {
   AtmData a;
   a.rho = par.rho_atm;
+  a.floor = par.rho_atm * (1.0 + 1e-6);
   a.p = par.atm_K * std::pow(par.rho_atm, par.atm_gamma);
   return a;
 }

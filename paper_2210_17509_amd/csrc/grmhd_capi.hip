@@ -920,6 +920,11 @@ int check_params(const grmhd_params* p, const grmhd_domain* dom, KPhys& ph) {
   ph.c2p_tol = p->c2p_tol;
   ph.c2p_maxit = p->c2p_maxit;
   ph.rho_atm = p->rho_atm;
+  // A state whose density is within a relative 1e-6 of rho_atm is taken as the
+  // atmosphere without a recovery: for the atmosphere state itself in a strong
+  // field the thermal energy lies below the rounding of tau, so whether its
+  // recovery succeeds would be decided by the last bit of tau.
+  ph.rho_floor = p->rho_atm * (1.0 + 1e-6);
   ph.p_atm = p->atm_K * std::pow(p->rho_atm, p->atm_gamma);
   ph.eps_atm = ph.p_atm / ((p->eos_gamma - 1.0) * p->rho_atm);
   return GRMHD_OK;

@@ -72,6 +72,7 @@ struct KPhys {
   double weno_eps, wenoz_eps;
   double c2p_tol;
   double rho_atm, p_atm, eps_atm;
+  double rho_floor;  // densities below rho_atm (1 + 1e-6) are the atmosphere
   int32_t c2p_maxit, wenoz_p;
 };
 
@@ -861,7 +862,7 @@ __device__ int c2p_cell(const double* g, const double* gi, double sqrtg, const K
   const double is = rcp_r(sqrtg);
   C2PIn c;
   c.Dt = U[0] * is;
-  if (c.Dt < ph.rho_atm) {
+  if (c.Dt < ph.rho_floor) {
     c2p_atmosphere(g, sqrtg, ph, U, P);
     return C2P_FLOOR;
   }
@@ -920,7 +921,7 @@ __device__ int c2p_cell(const double* g, const double* gi, double sqrtg, const K
     c2p_atmosphere(g, sqrtg, ph, U, P);
     return st;
   }
-  if (Pn[0] < ph.rho_atm) {
+  if (Pn[0] < ph.rho_floor) {
     c2p_atmosphere(g, sqrtg, ph, U, P);
     return C2P_FLOOR;
   }

@@ -187,6 +187,29 @@ def test_rk_step_parity(orc, case):
     assert int(d.host(d.nfail)[0]) == nf_o
 
 
+@pytest.mark.parametrize("scheme", [0, 1, 2])
+def test_rk_step_through_con2prim_failures(orc, scheme):
+    """The flat jump recipe at 32^3 (magnetisation up to about 30) over 6 steps:
+    from step 4 on, con2prim fails in a growing set of cells inside the fused
+    stages (22 cells over the 6 SSPRK3 steps in the oracle) and those cells are
+    reset to the atmosphere mid-step.  The failure count must be the oracle's
+    exactly and the fields, atmosphere cells and their neighbours included, the
+    oracle's to the FP64 bar."""
+    prob = I.config0(n=32)
+    steps = 6
+    d = H.Dev(prob)
+    d.step(steps, scheme=scheme)
+    Uo, Po = orc.prim2con(prob), prob.P.copy()
+    rate_o, nf_o = orc.rk_step(prob, Uo, Po, steps=steps, scheme=scheme)
+    nf_g = int(d.host(d.nfail)[0])
+    print(f"scheme {scheme}: n_fail gpu {nf_g} oracle {nf_o}", flush=True)
+    assert nf_o > 0
+    assert nf_g == nf_o
+    _assert_close(H.interior_fields(prob, d.host(d.U)), H.interior_fields(prob, Uo), TOL, "U")
+    _assert_close(H.interior_fields(prob, d.host(d.P)), H.interior_fields(prob, Po), TOL, "P")
+    assert float(d.host(d.rate)[0]) == pytest.approx(rate_o, rel=1e-12)
+
+
 def test_ssprk2_and_checkpoints(orc):
     import torch
     prob = I.config1(n=20)

@@ -295,6 +295,30 @@ def test_c2p_atmosphere_and_failures(orc):
     assert Pr[0] == par.rho_atm
 
 
+def test_c2p_atmosphere_state_is_a_fixed_point(orc):
+    """A cell already reset to the atmosphere in a strong field (B^2 ~ 1, so the
+    atmosphere's thermal energy rho eps ~ 1e-18 lies below the rounding of
+    tau ~ B^2 / 2) is recognised by its density and left as it is (status FLOOR,
+    U unchanged); a density 1% above rho_atm with the same field is recovered."""
+    par = _params(2.0)
+    p_atm = par.atm_K * par.rho_atm ** par.atm_gamma
+    eps_atm = p_atm / ((2.0 - 1.0) * par.rho_atm)
+    for B in ([1.0, 0.5, -0.3], [0.2, -0.9, 0.7]):
+        Pa = np.array([par.rho_atm, 0, 0, 0, eps_atm] + B)
+        Ua = orc.point_p2c(Pa, 2.0)
+        assert Ua[4] - 0.5 * float(np.dot(B, B)) < 4 * np.spacing(Ua[4])  # the energy is all magnetic, to rounding
+        Pr, Ur, st = orc.point_c2p(Ua, Pa, par)
+        assert st == 1
+        np.testing.assert_array_equal(Pr, Pa)
+        np.testing.assert_array_equal(Ur, Ua)
+    # just above the floor, weak field: an ordinary recovery
+    P1 = np.array([1.01 * par.rho_atm, 0.1, 0, 0, 1.0, 1e-6, 0, 0])
+    U1 = orc.point_p2c(P1, 2.0)
+    Pr, _, st = orc.point_c2p(U1, P1 * 0.99, par)
+    assert st == 0
+    np.testing.assert_allclose(Pr, P1, rtol=1e-10, atol=1e-20)
+
+
 # ---------------------------------------------------------------- Newman-Hamlin map alone
 
 def _nh_cases():
