@@ -113,8 +113,8 @@ def test_workspace_size(lib):
     assert G._lib.grmhd_workspace_bytes(ctypes.byref(d), ctypes.byref(par), 0, 0) == 2 * 8 * 8 * d.cell_stride + 256
     assert G._lib.grmhd_workspace_bytes(ctypes.byref(d), ctypes.byref(par), 0, 1) == 2 * 8 * 8 * d.cell_stride
     # starting from the caller's primitives, SSPRK3 needs a second primitive buffer
-    # classic RK4: stage state, its L and the accumulated step
-    assert G._lib.grmhd_workspace_bytes(ctypes.byref(d), ctypes.byref(par), 2, 0) == 3 * 8 * 8 * d.cell_stride + 256
+    # classic RK4 (stages fused): stage state, accumulated step and two primitive buffers
+    assert G._lib.grmhd_workspace_bytes(ctypes.byref(d), ctypes.byref(par), 2, 0) == 4 * 8 * 8 * d.cell_stride + 256
     par.p_current = 1
     assert G._lib.grmhd_workspace_bytes(ctypes.byref(d), ctypes.byref(par), 0, 0) == 3 * 8 * 8 * d.cell_stride + 256
     assert G._lib.grmhd_workspace_bytes(ctypes.byref(d), ctypes.byref(par), 1, 0) == 2 * 8 * 8 * d.cell_stride + 256
