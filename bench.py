@@ -44,7 +44,7 @@ WORKLOADS = {
     "setupA152": dict(kind="setupA", n=152, scheme=1, paper_v100=0.44e8,
                       desc="setupA stand-in: static curved metric 152^3, Gamma-law, WENO5, HLLE, RK2 (SSPRK2), "
                            "periodic, FP64"),
-    # classic RK4 (con2prim as its own launch per stage, L, combine)
+    # classic RK4 (stages fused like the SSPRK ones: L, accumulation, next stage state, con2prim)
     "curved256-rk4": dict(kind="config1", n=256, scheme=2,
                           desc="static curved metric 256^3, WENO5, HLLE, FP64, classic RK4"),
     "setupA240": dict(kind="setupA", n=240, scheme=1, paper_v100=0.47e8,
