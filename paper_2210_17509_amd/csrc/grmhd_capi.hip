@@ -785,12 +785,20 @@ struct TimeScope {
     if (g_timed.size() > 4096) drain_timing();
     a = pool_event();
     b = pool_event();
-    if (a) hipEventRecord(a, s);
+    if (!a || !b || hipEventRecord(a, s) != hipSuccess) release();  // this launch goes untimed
   }
   ~TimeScope() {
     if (!a || !b) return;
-    hipEventRecord(b, s);
+    if (hipEventRecord(b, s) != hipSuccess) {
+      release();
+      return;
+    }
     g_timed.push_back({a, b, kind});
+  }
+  void release() {
+    if (a) g_event_pool.push_back(a);
+    if (b) g_event_pool.push_back(b);
+    a = b = nullptr;
   }
 };
 
@@ -947,7 +955,10 @@ Table make_table(const grmhd_domain* dom) {
 int persistent_blocks() {
   static int n = [] {
     int dev = 0, cus = 256;
-    if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    int n = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0)
+      cus = n;
     return cus;
   }();
   return n;
