@@ -272,22 +272,38 @@ template <int D, int RECON, bool SHIFT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_adj_face(AdjArgs a) {
   const int nb = a.tab.nbox;
   const int32_t* pre = a.tab.face_prefix + D * (nb + 1);
-  // y faces: each XCD takes a contiguous run of face blocks, so the blocks of
-  // neighbouring grid rows (overlapping stencils) share its L2 (timed: no gain
-  // for x faces, a loss for z faces)
-  const int blk = (D == 1) ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+  // y and z faces: each XCD takes a contiguous run of face blocks, so blocks
+  // with overlapping stencils share its L2
+  const int blk = (D != 0) ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
   const int b = find_box(pre, nb, blk);
   const KBox& bx = a.tab.box[b];
   const int nfx = bx.n[0] + (D == 0), nfy = bx.n[1] + (D == 1), nfz = bx.n[2] + (D == 2);
-  // Lanes past the box's last face take part (with nothing to add) in the
-  // wave-level exchange of the x faces below.
-  const int lin_raw = (blk - pre[b]) * FACE_BLOCK + threadIdx.x;
-  const bool live = lin_raw < nfx * nfy * nfz;
-  const int lin = live ? lin_raw : 0;
-  const int i = lin % nfx;
-  const int r = lin / nfx;
-  const int j = r % nfy;
-  const int k = r / nfy;
+  int i, j, k;
+  bool live;
+  // x faces: a block is FACE_BLOCK consecutive faces in storage order.  Lanes
+  // past the box's last face take part (with nothing to add) in the wave-level
+  // exchange of the x faces below.
+  // y and z faces: a block is a patch of ADJ_PX faces along x by ADJ_PD faces
+  // along D (lane = x fastest) at one index of the third axis.
+  const int nfD = (D == 1) ? nfy : nfz;
+  const int pbx = (bx.n[0] + ADJ_PX - 1) / ADJ_PX, pbd = (nfD + ADJ_PD - 1) / ADJ_PD;
+  const int local = blk - pre[b];
+  const int px = local % pbx, pd = (local / pbx) % pbd, po = local / (pbx * pbd);
+  if constexpr (D == 0) {
+    const int lin_raw = local * FACE_BLOCK + threadIdx.x;
+    live = lin_raw < nfx * nfy * nfz;
+    const int lin = live ? lin_raw : 0;
+    i = lin % nfx;
+    const int r = lin / nfx;
+    j = r % nfy;
+    k = r / nfy;
+  } else {
+    const int ix = px * ADJ_PX + (int)threadIdx.x % ADJ_PX, id = pd * ADJ_PD + (int)threadIdx.x / ADJ_PX;
+    live = ix < bx.n[0] && id < nfD;
+    i = live ? ix : 0;
+    j = (D == 1) ? (live ? id : 0) : po;
+    k = (D == 2) ? (live ? id : 0) : po;
+  }
   const int ng = bx.ng;
   const int c = (D == 0) ? i : (D == 1 ? j : k);
   const int nD = bx.n[D];
@@ -316,10 +332,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     Fb[q] = live ? (vr - vl) * id : 0.0;
     any = any || (Fb[q] != 0.0);
   }
-  if (!__any(any)) return;  // the whole wave has nothing to propagate
+  // y and z faces add their stencil contributions into an LDS patch of the
+  // ADJ_PD + 5 cell rows along D that the block's faces reach (all 8 fields),
+  // and the patch is added to Pbar with one atomic per nonzero element at the
+  // end (instead of an atomic per contribution).  Row r of the patch is the cell
+  // pd * ADJ_PD - 3 + r along D.
+  __shared__ double spatch[(D == 0) ? 1 : 8 * ADJ_ROWS * (ADJ_PX + 1)];
+  if constexpr (D != 0) {
+    for (int e = threadIdx.x; e < 8 * ADJ_ROWS * (ADJ_PX + 1); e += FACE_BLOCK) spatch[e] = 0.0;
+    __syncthreads();
+  }
+  const bool skip = !__any(any);  // the whole wave has nothing to propagate
+  if constexpr (D == 0) {
+    if (skip) return;
+  }
   double qbL[8], qbR[8];
-  bool fbL, fbR;
-  face_side_adjoints<D, RECON, SHIFT>(a, bx, Pb, idx, i, j, k, Fb, qbL, qbR, fbL, fbR);
+  bool fbL = false, fbR = false;
+  if (!skip) face_side_adjoints<D, RECON, SHIFT>(a, bx, Pb, idx, i, j, k, Fb, qbL, qbR, fbL, fbR);
   const double eps = (RECON >= GRMHD_RECON_WENOZ) ? a.ph.wenoz_eps : a.ph.weno_eps;
   // x faces: a wave holds consecutive faces of one grid line, so the lane of the
   // face just below cell m (the cell's "owner") gathers the contributions of its
@@ -347,7 +376,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     for (int o = O0; o < O1; ++o) snx[o] = Pb[idx[o]];
   }
 #pragma clang loop unroll(disable)
-  for (int q = 0; q < 8; ++q) {
+  for (int q = 0; q < 8 && !skip; ++q) {
     double s[6] = {0, 0, 0, 0, 0, 0};
     if constexpr (D == 0) {
 #pragma unroll
@@ -380,9 +409,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
       }
       if (own != 0.0) unsafeAtomicAdd(Gb + q * a.cs + idx[3], own);
     } else {
+      const int lx = (int)threadIdx.x % ADJ_PX, ld = (int)threadIdx.x / ADJ_PX;
 #pragma unroll
       for (int o = 0; o < 6; ++o)
-        if (sb[o] != 0.0) unsafeAtomicAdd(Gb + q * a.cs + idx[o], sb[o]);
+        if (sb[o] != 0.0) atomicAdd(&spatch[(q * ADJ_ROWS + ld + o) * (ADJ_PX + 1) + lx], sb[o]);
+    }
+  }
+  if constexpr (D != 0) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < 8 * ADJ_ROWS * ADJ_PX; e += FACE_BLOCK) {
+      const int lx = e % ADJ_PX, rr = (e / ADJ_PX) % ADJ_ROWS, q = e / (ADJ_PX * ADJ_ROWS);
+      const double v = spatch[(q * ADJ_ROWS + rr) * (ADJ_PX + 1) + lx];
+      if (v == 0.0) continue;
+      const int ix = px * ADJ_PX + lx;
+      const int m = pd * ADJ_PD - 3 + rr;  // cell index along D (ghost rows map to the cells they copy)
+      const int mm = (m < 0) ? bx.mlo[D][m + 3] : (m >= nD ? bx.mhi[D][m - nD] : m);
+      const int cell = (D == 1) ? ((po + ng) * bx.NXY + (mm + ng) * bx.NX + (ix + ng))
+                                : ((mm + ng) * bx.NXY + (po + ng) * bx.NX + (ix + ng));
+      unsafeAtomicAdd(Gb + q * a.cs + cell, v);
     }
   }
 }
@@ -1149,8 +1193,13 @@ int grmhd_domain_prepare(const grmhd_domain* dom, void* stream) {
     }
     for (int d = 0; d < 3; ++d) {
       fp[d * (nb + 1) + b] = (int32_t)acc_f[d];
-      const int64_t nf = int64_t(x.n[0] + (d == 0)) * (x.n[1] + (d == 1)) * (x.n[2] + (d == 2));
-      acc_f[d] += (nf + FACE_BLOCK - 1) / FACE_BLOCK;
+      if (d == 0) {
+        const int64_t nf = int64_t(x.n[0] + 1) * x.n[1] * x.n[2];
+        acc_f[d] += (nf + FACE_BLOCK - 1) / FACE_BLOCK;
+      } else {  // patches of ADJ_PX x ADJ_PD faces at each index of the third axis
+        const int64_t nfd = x.n[d] + 1, nother = (d == 1) ? x.n[2] : x.n[1];
+        acc_f[d] += int64_t((x.n[0] + ADJ_PX - 1) / ADJ_PX) * ((nfd + ADJ_PD - 1) / ADJ_PD) * nother;
+      }
     }
     vp[b] = (int32_t)acc_v;
     const int64_t nvp = int64_t(x.n[0] + 1) * (x.n[1] + 1) * (x.n[2] + 1);

@@ -33,6 +33,11 @@ struct KBox {
 static_assert(sizeof(KBox) % 8 == 0, "KBox alignment");
 
 constexpr int FACE_BLOCK = 256;
+// face-adjoint blocks of y and z faces: patches of ADJ_PX faces along x by ADJ_PD
+// along the face direction (ADJ_PX * ADJ_PD = FACE_BLOCK); their stencils reach
+// ADJ_ROWS cell rows along that direction
+constexpr int ADJ_PX = 16, ADJ_PD = 16, ADJ_ROWS = ADJ_PD + 5;
+static_assert(ADJ_PX * ADJ_PD == FACE_BLOCK, "one face per thread");
 
 struct TableHeader {
   uint64_t magic;
@@ -51,7 +56,7 @@ struct Table {
   const KBox* box;
   const int32_t* c2p_prefix;
   const int32_t* tile_prefix;  // [NTILE][nbox+1]
-  const int32_t* face_prefix;  // [3][nbox+1], blocks of FACE_BLOCK faces per direction
+  const int32_t* face_prefix;  // [3][nbox+1], face-adjoint blocks per direction (x: FACE_BLOCK faces; y, z: patches)
   const int32_t* vert_prefix;  // blocks of C2P_BLOCK interior vertex points (n+1 per axis)
   int32_t nbox;
 };

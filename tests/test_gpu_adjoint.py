@@ -46,7 +46,15 @@ def _thin():
                    params=I.Params(recon=I.RECON_WENOZ, eos_gamma=2.0))
 
 
+def _patches_box():
+    """Flat WENO-Z box whose y and z face adjoints take several 16 x 16 face
+    patches per direction, the last ones partial, with periodic and outflow faces."""
+    bc = (I.BC_PERIODIC, I.BC_PERIODIC, I.BC_OUTFLOW, I.BC_OUTFLOW, I.BC_PERIODIC, I.BC_PERIODIC)
+    return T.build((37, 35, 20), T.smooth_fields(15, 5.0 / 3.0), bc=bc, params=I.Params(recon=I.RECON_WENOZ))
+
+
 CASES = {
+    "wenoz_patches": _patches_box,
     "wenoz_flat": lambda: I.config4(n=10),
     "wenoz_thin_box": _thin,
     "weno5_curved": _smooth_curved,
@@ -96,6 +104,23 @@ def test_adjoint_matches_oracle_jvp(orc, case, scheme):
         rhs = np.sum(gin * dU * mask)
         ref = np.sum(np.abs(gout * jd * mask))
         assert abs(lhs - rhs) <= 1e-10 * ref, (case, lhs, rhs, ref)
+
+
+def test_adjoint_of_a_batch_is_the_boxes_adjoints():
+    """The boxes of a batch are independent, so the adjoint of a batched step is
+    the concatenation of the boxes' own adjoints (to the atomics' summation order)."""
+    from tests.test_gpu_batched import _single
+    prob = I.config2(nbox=4, seed=41, edges=(6, 12, 20, 33))
+    mask = _interior_mask(prob)
+    gout = np.random.default_rng(5).standard_normal(prob.P.shape) * mask
+    gin = _gpu_adjoint(prob, gout)
+    for b, bx in enumerate(prob.boxes):
+        c0 = prob.cell_off[b]
+        gb = _gpu_adjoint(_single(prob, b), gout[:, c0:c0 + bx.ncell])
+        m = I.interior_mask(bx).ravel()
+        ref = gb[:, m]
+        got = gin[:, c0:c0 + bx.ncell][:, m]
+        assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max(), (b, bx.n)
 
 
 @pytest.mark.parametrize("p_current", [0, 1])
