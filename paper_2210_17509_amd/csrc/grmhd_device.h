@@ -36,7 +36,7 @@ constexpr int FACE_BLOCK = 256;
 // face-adjoint blocks of y and z faces: patches of ADJ_PX faces along x by ADJ_PD
 // along the face direction (ADJ_PX * ADJ_PD = FACE_BLOCK); their stencils reach
 // ADJ_ROWS cell rows along that direction
-constexpr int ADJ_PX = 16, ADJ_PD = 16, ADJ_ROWS = ADJ_PD + 5;
+constexpr int ADJ_PX = 32, ADJ_PD = 8, ADJ_ROWS = ADJ_PD + 5;
 static_assert(ADJ_PX * ADJ_PD == FACE_BLOCK, "one face per thread");
 
 struct TableHeader {

@@ -47,8 +47,9 @@ def _thin():
 
 
 def _patches_box():
-    """Flat WENO-Z box whose y and z face adjoints take several 16 x 16 face
-    patches per direction, the last ones partial, with periodic and outflow faces."""
+    """Flat WENO-Z box whose face adjoints take several face patches per
+    direction (32 faces across by 8 along y or z), the last ones partial, with
+    periodic and outflow faces."""
     bc = (I.BC_PERIODIC, I.BC_PERIODIC, I.BC_OUTFLOW, I.BC_OUTFLOW, I.BC_PERIODIC, I.BC_PERIODIC)
     return T.build((37, 35, 20), T.smooth_fields(15, 5.0 / 3.0), bc=bc, params=I.Params(recon=I.RECON_WENOZ))
 
