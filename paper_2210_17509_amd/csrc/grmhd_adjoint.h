@@ -329,7 +329,7 @@ __device__ __forceinline__ void weno5_vjp(const double* s, double eps, int zp, d
       w[k] = dk[k] * f[k] * t[(k + 1) % 3] * t[(k + 2) % 3];
     }
   }
-  const double i6W = 1.0 / (6.0 * (w[0] + w[1] + w[2]));
+  const double i6W = rcp_r(6.0 * (w[0] + w[1] + w[2]));
   const double qv = (w[0] * q[0] + w[1] * q[1] + w[2] * q[2]) * i6W;
   // reverse: value -> weights -> e_k^p (or (eps + beta_k)^2) -> beta_k
   double wb[3];
@@ -414,8 +414,8 @@ __device__ __forceinline__ void side_vjp(const FaceMetric<double>& m, const doub
   }
   const double v2 = vl[0] * v[0] + vl[1] * v[1] + vl[2] * v[2];
   const double om = 1.0 - v2;
-  const double iW = sqrt(om);
-  const double W = 1.0 / iW;
+  const double iW = sqrt_r(om);
+  const double W = rcp_r(iW);
   const double B2 = Bl[0] * B[0] + Bl[1] * B[1] + Bl[2] * B[2];
   const double Bv = Bl[0] * v[0] + Bl[1] * v[1] + Bl[2] * v[2];
   const double ab0 = W * Bv;
@@ -423,19 +423,22 @@ __device__ __forceinline__ void side_vjp(const FaceMetric<double>& m, const doub
   const double b2 = (B2 + ab0 * ab0) * iW2;
   const double p = gm1 * rho * eps;
   const double rhoh = rho * (1.0 + eps) + p;
-  // speeds
-  const double cs2 = gam * p / rhoh;
+  // speeds (one reciprocal for c_s^2 and c_a^2, as in side_speeds)
   const double qq = rhoh + b2;
-  const double ca2 = b2 / qq;
+  const double ir = rcp_r(rhoh * qq);
+  const double irhoh = qq * ir, iqq = rhoh * ir;
+  const double cs2 = gam * p * qq * ir;
+  const double ca2 = b2 * rhoh * ir;
   const double cf2 = cs2 + ca2 - cs2 * ca2;
   const double vd = v[D];
   const double den = 1.0 - v2 * cf2;
   const double X = m.gdd * den - vd * vd * (1.0 - cf2);
   const double disc = om * X;
   const double dc = disc < 0.0 ? 0.0 : disc;
-  const double root = sqrt(cf2 * dc);
+  const double root = sqrt_r(cf2 * dc);
   const double base = vd * (1.0 - cf2);
-  const double ad = m.alpha / den;
+  const double iden = rcp_r(den);
+  const double ad = m.alpha * iden;
   // cons / flux
   const double W2 = W * W;
   const double rhohs = rhoh + b2;
@@ -451,7 +454,7 @@ __device__ __forceinline__ void side_vjp(const FaceMetric<double>& m, const doub
   U[4] = sg * (rhohs * W2 - Ps - ab0 * ab0) - U[0];
 #pragma unroll
   for (int k = 0; k < 3; ++k) U[5 + k] = sg * B[k];
-  const double ia = 1.0 / al;
+  const double ia = m.ialpha;
   double vt[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) vt[i] = v[i] - m.beta[i] * ia;
@@ -540,12 +543,12 @@ __device__ __forceinline__ void side_vjp(const FaceMetric<double>& m, const doub
   const double adb = lsum;
   const double baseb = (lpb + lmb) * ad;
   const double rootb = (lpb - lmb) * ad;
-  double denb = -adb * ad / den;
+  double denb = -adb * ad * iden;
   double vdb = baseb * (1.0 - cf2);
   double cf2b = -baseb * vd;
   double dcb = 0.0;
   if (root > 0.0) {
-    const double r2b = rootb / (2.0 * root);
+    const double r2b = rootb * 0.5 * rcp_r(root);
     cf2b += r2b * dc;
     dcb = r2b * cf2;
   }
@@ -560,10 +563,10 @@ __device__ __forceinline__ void side_vjp(const FaceMetric<double>& m, const doub
   vb_[D] += vdb;
   const double cs2b = cf2b * (1.0 - ca2);
   const double ca2b = cf2b * (1.0 - cs2);
-  b2b += ca2b * (1.0 - ca2) / qq;
-  rhohb -= ca2b * ca2 / qq;
-  pb += cs2b * gam / rhoh;
-  rhohb -= cs2b * cs2 / rhoh;
+  b2b += ca2b * (1.0 - ca2) * iqq;
+  rhohb -= ca2b * ca2 * iqq;
+  pb += cs2b * gam * irhoh;
+  rhohb -= cs2b * cs2 * irhoh;
   // state
   rhob += rhohb * (1.0 + eps);
   double epsb = rhohb * rho;
@@ -583,7 +586,7 @@ __device__ __forceinline__ void side_vjp(const FaceMetric<double>& m, const doub
     Bb_[i] += B2b * Bl[i];
   }
   iWb += -Wb * W * W;
-  omb += iWb / (2.0 * iW);
+  omb += iWb * 0.5 * W;
   v2b -= omb;
 #pragma unroll
   for (int i = 0; i < 3; ++i) {

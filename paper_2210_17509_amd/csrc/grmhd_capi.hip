@@ -239,7 +239,7 @@ __device__ __forceinline__ void face_side_adjoints(const AdjArgs& a, const KBox&
   double gFL[8], gFR[8], gUL[8], gUR[8];
   double xbp = 0.0, xbm = 0.0;
   if (den > 0.0) {
-    const double idn = 1.0 / den;
+    const double idn = rcp_r(den);
     const double xx = xip * xim;
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
