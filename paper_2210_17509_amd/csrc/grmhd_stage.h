@@ -39,9 +39,11 @@ struct StageArgs {
   Table tab;
   int tile;
   const double* __restrict__ P;
-  const double* __restrict__ Us;
-  const double* __restrict__ Un;
-  double* __restrict__ Uout;
+  // Us, Un and Uout alias (an in-place stage writes the state it reads), so
+  // they carry no restrict
+  const double* Us;
+  const double* Un;
+  double* Uout;
   const double* __restrict__ alpha;
   const double* __restrict__ beta;
   const double* __restrict__ gamma;
