@@ -854,7 +854,15 @@ __device__ __forceinline__ void c2p_atmosphere(const double* g, double sqrtg, co
 }
 
 // Full recovery of one cell: U (in/out: atmosphere rewrites it), P (guess in, result out).
-__device__ int c2p_cell(const double* g, const double* gi, double sqrtg, const KPhys& ph, double U[8], double P[8]) {
+// With REFETCH, (*mf)(g, gi, sqrtg) re-points the metric after the Newton
+// iteration (which does not use it), so a caller that can recompute the metric
+// cheaply need not hold it in registers across the iteration.
+struct NoRefetch {
+  __device__ void operator()(const double*&, const double*&, double&) const {}
+};
+template <bool REFETCH = false, typename MF = NoRefetch>
+__device__ int c2p_cell(const double* g, const double* gi, double sqrtg, const KPhys& ph, double U[8], double P[8],
+                        const MF* mf = nullptr) {
   bool fin = true;
 #pragma unroll
   for (int q = 0; q < 8; ++q) fin = fin && dfinite(U[q]);
@@ -912,7 +920,9 @@ __device__ int c2p_cell(const double* g, const double* gi, double sqrtg, const K
   int st = C2P_NOCONV;
   {
     double W1 = W, z1 = z, T1 = T;
-    if (c2p_newton(c, ph, W1, z1, T1)) st = c2p_recover(c, g, gi, ph.gm1, W1, z1, T1, Pn);
+    const bool conv = c2p_newton(c, ph, W1, z1, T1);
+    if constexpr (REFETCH) (*mf)(g, gi, sqrtg);
+    if (conv) st = c2p_recover(c, g, gi, ph.gm1, W1, z1, T1, Pn);
   }
   if (st != C2P_OK) {
     double W2, z2, T2;
