@@ -271,7 +271,11 @@ __device__ __forceinline__ void direction_phase(const StageArgs& a, const KBox& 
 #pragma unroll
     for (int q = 0; q < 8; ++q) acc[q] += (sF[q][lo] - sF[q][hi]) * idx;
   }
-  __syncthreads();
+  // The next direction rewrites sF.  After the last one nothing in this tile
+  // does, and the next tile of a persistent workgroup starts behind barriers,
+  // so FP64 instances go on to the cell update without waiting (0.5% faster);
+  // the FP32 instances keep the barrier (dropping it there was 2% slower).
+  if constexpr (D != 2 || sizeof(R) != 8) __syncthreads();
 }
 
 template <int RECON, typename R, bool SHIFT, int TI, bool BF = false>
