@@ -364,28 +364,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     take[o] = (D == 0) && live && c < nD && from >= 0 && from < 64 && fc >= 0 && fc <= nD;
   }
   // reverse of the reconstruction, scattered onto the stencil cells, one field at
-  // a time (only one stencil is live).  x faces prefetch the next field's
-  // stencil during the current field's work (timed faster there; for y and z
-  // faces the extra live registers cost more than the hidden latency).  The
-  // per-field adjoints are shifted down one slot per iteration so every
-  // register index is static.
+  // a time (only one stencil is live; prefetching the next field's stencil
+  // costs more in registers than it hides).  The per-field adjoints are shifted
+  // down one slot per iteration so every register index is static.
   constexpr int O0 = (RECON == GRMHD_RECON_MINMOD) ? 1 : 0, O1 = (RECON == GRMHD_RECON_MINMOD) ? 5 : 6;
-  double snx[6] = {0, 0, 0, 0, 0, 0};
-  if constexpr (D == 0) {
-#pragma unroll
-    for (int o = O0; o < O1; ++o) snx[o] = Pb[idx[o]];
-  }
+
 #pragma clang loop unroll(disable)
   for (int q = 0; q < 8 && !skip; ++q) {
     double s[6] = {0, 0, 0, 0, 0, 0};
     if constexpr (D == 0) {
+      const double* __restrict__ f = Pb + q * a.cs;
 #pragma unroll
-      for (int o = 0; o < 6; ++o) s[o] = snx[o];
-      if (q < 7) {
-        const double* __restrict__ fn = Pb + (q + 1) * a.cs;
-#pragma unroll
-        for (int o = O0; o < O1; ++o) snx[o] = fn[idx[o]];
-      }
+      for (int o = O0; o < O1; ++o) s[o] = f[idx[o]];
     } else {
       const double* __restrict__ f = Pb + q * a.cs;
 #pragma unroll
