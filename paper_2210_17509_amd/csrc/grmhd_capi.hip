@@ -284,11 +284,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   // past the box's last face take part (with nothing to add) in the wave-level
   // exchange of the x faces below.
   // y and z faces: a block is a patch of ADJ_PX faces along x by ADJ_PD faces
-  // along D (lane = x fastest) at one index of the third axis.
-  const int nfD = (D == 1) ? nfy : nfz;
-  const int pbx = (bx.n[0] + ADJ_PX - 1) / ADJ_PX, pbd = (nfD + ADJ_PD - 1) / ADJ_PD;
+  // along D (lane = x fastest) at one index po of the third axis; px, pd: the
+  // patch's indices along x and D.
   const int local = blk - pre[b];
-  const int px = local % pbx, pd = (local / pbx) % pbd, po = local / (pbx * pbd);
+  int px = 0, pd = 0, po = 0;
   if constexpr (D == 0) {
     const int lin_raw = local * FACE_BLOCK + threadIdx.x;
     live = lin_raw < nfx * nfy * nfz;
@@ -298,6 +297,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     j = r % nfy;
     k = r / nfy;
   } else {
+    const int nfD = (D == 1) ? nfy : nfz;
+    const int pbx = (bx.n[0] + ADJ_PX - 1) / ADJ_PX, pbd = (nfD + ADJ_PD - 1) / ADJ_PD;
+    px = local % pbx;
+    pd = (local / pbx) % pbd;
+    po = local / (pbx * pbd);
     const int ix = px * ADJ_PX + (int)threadIdx.x % ADJ_PX, id = pd * ADJ_PD + (int)threadIdx.x / ADJ_PX;
     live = ix < bx.n[0] && id < nfD;
     i = live ? ix : 0;
@@ -372,15 +376,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 #pragma clang loop unroll(disable)
   for (int q = 0; q < 8 && !skip; ++q) {
     double s[6] = {0, 0, 0, 0, 0, 0};
-    if constexpr (D == 0) {
-      const double* __restrict__ f = Pb + q * a.cs;
+    const double* __restrict__ f = Pb + q * a.cs;
 #pragma unroll
-      for (int o = O0; o < O1; ++o) s[o] = f[idx[o]];
-    } else {
-      const double* __restrict__ f = Pb + q * a.cs;
-#pragma unroll
-      for (int o = O0; o < O1; ++o) s[o] = f[idx[o]];
-    }
+    for (int o = O0; o < O1; ++o) s[o] = f[idx[o]];
     const double aL = qbL[0], aR = qbR[0];
 #pragma unroll
     for (int t = 0; t < 7; ++t) {
@@ -401,8 +399,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     } else {
       const int lx = (int)threadIdx.x % ADJ_PX, ld = (int)threadIdx.x / ADJ_PX;
 #pragma unroll
-      for (int o = 0; o < 6; ++o)
-        if (sb[o] != 0.0) atomicAdd(&spatch[(q * ADJ_ROWS + ld + o) * (ADJ_PX + 1) + lx], sb[o]);
+      for (int o = 0; o < 6; ++o)  // only faces that exist add (their rows stay within the ghost maps)
+        if (live && sb[o] != 0.0) atomicAdd(&spatch[(q * ADJ_ROWS + ld + o) * (ADJ_PX + 1) + lx], sb[o]);
     }
   }
   if constexpr (D != 0) {
