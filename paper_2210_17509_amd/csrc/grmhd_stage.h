@@ -287,13 +287,13 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int tg,
   const int b = find_box(a.tab.tile_prefix + TI * (a.tab.nbox + 1), a.tab.nbox, tg);
   const KBox& bx = a.tab.box[b];
   const int t = tg - a.tab.tile_prefix[TI * (a.tab.nbox + 1) + b];
-  // Tile walk: x fastest, then y within a strip of SH tile rows, then z, then
-  // the next strip.  A contiguous run of tiles (one XCD's share) thus marches
-  // up z through a strip about as wide as the tiles one XCD holds at once, so
-  // the z-halo rows a tile layer loads are still in that XCD's L2 when the
-  // next layer needs them as its own cells.
+  // Tile walk: x fastest, then y within a strip of SH tile rows (about 64
+  // tiles), then z, then the next strip.  A contiguous run of tiles (one XCD's
+  // share) thus marches up z through a strip narrower than the 96 tiles one XCD
+  // holds at once, so the z-halo rows a tile layer loads are still in that
+  // XCD's L2 when the next layer needs them as its own cells.
   const int ntx = (bx.n[0] + TX - 1) / TX, nty = (bx.n[1] + TY - 1) / TY, ntz = (bx.n[2] + TZ - 1) / TZ;
-  const int SH = max(1, min(nty, 128 / ntx));
+  const int SH = max(1, min(nty, 64 / ntx));
   const int r = t / ntx, st = r / (SH * ntz), h = min(SH, nty - st * SH), r3 = r - st * SH * ntz;
   const int org[3] = {(t % ntx) * TX, (st * SH + r3 % h) * TY, (r3 / h) * TZ};
   const int tid = threadIdx.x;

@@ -4,7 +4,7 @@
   launch configuration (steps from the current primitives, default tile and
   schedule), every one of its 16.8 M cells;
 - a 112^3 grid whose tile walk needs several strips with a partial last one
-  (28 tile rows of 16x4x3 tiles in strips of 18);
+  (28 tile rows of 16x4x3 tiles in strips of 9);
 - the 400-box batch, every cell of every box, stepped as the benchmark steps it
   (autotuned tile shape and schedule, the step captured in a graph);
 - mixed precision: 50 SSPRK3 steps of the 384^3 workload's recipe and spacing
@@ -72,7 +72,7 @@ def test_curved256_every_cell(orc16):
 def test_partial_last_strip_every_cell(orc16):
     prob = I.config1(n=112, seed=I.SEED_BASE + 112)
     ntx, nty = -(-112 // 16), -(-112 // 4)
-    sh = max(1, min(nty, 128 // ntx))
+    sh = max(1, min(nty, 64 // ntx))
     assert nty > sh and nty % sh != 0  # several strips, the last one partial
     d = _step_current_prims(prob, steps=2)
     Uo, Po = orc16.prim2con(prob), prob.P.copy()
