@@ -16,3 +16,19 @@ def test_gpus_above_one_refused(monkeypatch, capsys):
         bench.main()
     assert e.value.code == 2
     assert "one GPU" in capsys.readouterr().err
+
+
+def test_committed_profiles_match_the_kernel_sources():
+    """The rocprofv3 summaries under profiles/ that record a kernel-source hash
+    were taken from the current kernel sources (else bench.py reports no HBM
+    traffic and the summaries describe other code)."""
+    import glob
+    import os
+    paths = sorted(glob.glob(os.path.join(bench.ROOT, "profiles", "*.txt")))
+    stamped = 0
+    for p in paths:
+        for line in open(p):
+            if line.startswith("kernel_source_sha256:"):
+                stamped += 1
+                assert line.split(":", 1)[1].strip() == bench.kernel_source_hash(), os.path.basename(p)
+    assert stamped >= 1
