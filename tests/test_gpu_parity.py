@@ -134,6 +134,53 @@ def test_con2prim_failures_and_atmosphere(orc):
     _assert_close(H.interior_fields(prob, d.host(d.U)), H.interior_fields(prob, Uo), TOL)
 
 
+def test_con2prim_atmosphere_state_is_a_fixed_point(orc):
+    """Cells already at the atmosphere in strong fields (B^2 up to ~1.4, so the
+    thermal energy lies below the rounding of tau) keep status FLOOR and their
+    U bit for bit, on the GPU as in the oracle; a density 1% above the floor is
+    recovered (status 0)."""
+    import torch
+    prob = I.config0(n=12)
+    par = prob.params
+    eps_atm = par.atm_K * par.rho_atm ** par.atm_gamma / ((par.eos_gamma - 1.0) * par.rho_atm)
+    U = orc.prim2con(prob)
+    bx = prob.boxes[0]
+    Uv, Pv = prob.box_view(U, 0), prob.box_view(prob.P, 0)
+    g = bx.ng
+    cells = [(g + 1, g + 2, g + 3), (g + 5, g + 4, g + 7), (g + 9, g + 9, g + 1)]
+    fields = [[1.0, 0.5, -0.3], [0.2, -0.9, 0.7], [-0.6, 0.1, 0.4]]
+    P0 = prob.P.copy()
+    P0v = prob.box_view(P0, 0)
+    for (k, j, i), B in zip(cells, fields):
+        Pa = np.array([par.rho_atm, 0, 0, 0, eps_atm] + B)
+        Uv[:, k, j, i] = orc.point_p2c(Pa, par.eos_gamma)
+        P0v[:, k, j, i] = Pa
+    k1, j1, i1 = g + 3, g + 8, g + 6  # 1% above the floor, weak field
+    P1 = np.array([1.01 * par.rho_atm, 0.1, 0, 0, 1.0, 1e-6, 0, 0])
+    Uv[:, k1, j1, i1] = orc.point_p2c(P1, par.eos_gamma)
+    P0v[:, k1, j1, i1] = P1 * 0.99
+    Uo, Po = U.copy(), P0.copy()
+    st_o, nf_o = orc.con2prim(prob, Uo, Po)
+    d = H.Dev(prob)
+    d.U.copy_(torch.as_tensor(U))
+    d.P.copy_(torch.as_tensor(P0))
+    status = torch.zeros(prob.cell_stride, dtype=torch.int32, device="cuda")
+    H.G().grmhd_con2prim(d.dom, d.par, d.met, d.U, d.P, status, d.nfail)
+    sg = d.host(status)
+    m = I.interior_mask(bx).ravel()
+    np.testing.assert_array_equal(sg[m], st_o[m])
+    nx, ny = bx.cdims[0], bx.cdims[1]
+    flat = lambda k, j, i: (k * ny + j) * nx + i
+    Ug = d.host(d.U)
+    for (k, j, i) in cells:
+        c = flat(k, j, i)
+        assert sg[c] == 1 and st_o[c] == 1
+        np.testing.assert_array_equal(Ug[:, c], U[:, c])
+    assert sg[flat(k1, j1, i1)] == 0
+    assert int(d.host(d.nfail)[0]) == nf_o
+    _assert_close(H.interior_fields(prob, d.host(d.P)), H.interior_fields(prob, Po), TOL)
+
+
 def test_con2prim_newman_hamlin_recovery(orc):
     """A strongly magnetised state behind a Balsara 2 shock (B^2 = 40, S^2 = 890)
     seeded with the pre-shock primitives: the 3D Newton diverges, the
