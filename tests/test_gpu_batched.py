@@ -110,6 +110,45 @@ def test_every_tile_and_schedule_matches_oracle(orc, recon):
             assert float(d.host(d.rate)[0]) == pytest.approx(rate_o, rel=1e-12)
 
 
+def _instances_box(shift, precision, recon, wenoz_p=1):
+    from tests import problems as T
+    beta = ((lambda X, Y, Z: [0.1 * np.sin(2 * np.pi * Y), 0.05 + 0 * X, -0.08 * np.cos(2 * np.pi * X)])
+            if shift else None)
+    met = T.conformal_metric(lambda X, Y, Z: 1.0 + 0.05 * np.sin(2 * np.pi * X) * np.cos(2 * np.pi * Z),
+                             alpha_fn=lambda X, Y, Z: 0.9 + 0.05 * np.cos(2 * np.pi * Y), beta_fn=beta)
+    bc = (I.BC_OUTFLOW, I.BC_OUTFLOW, I.BC_PERIODIC, I.BC_PERIODIC, I.BC_OUTFLOW, I.BC_OUTFLOW)
+    return T.build((37, 13, 11), T.smooth_fields(17, 2.0), met, bc=bc,
+                   params=I.Params(recon=recon, eos_gamma=2.0, precision=precision, wenoz_p=wenoz_p))
+
+
+@pytest.mark.parametrize("kind", ["shift-fp64-weno5", "noshift-mixed-weno5", "shift-mixed-wenoz", "noshift-fp64-wenoz2",
+                                  "noshift-mixed-minmod"])
+def test_every_instance_agrees_bitwise(kind):
+    """Every tile shape and schedule computes the same face numbers, so two SSPRK3
+    steps agree bit for bit with the default tile's grid launch: this checks
+    each compiled stage-kernel instance (shifted metric, FP32 faces, WENO-Z
+    with p = 2) against the one the parity tests compare with the oracle."""
+    shift = kind.startswith("shift")
+    precision = I.PREC_MIXED if "mixed" in kind else I.PREC_FP64
+    recon = {"weno5": I.RECON_WENO5, "wenoz": I.RECON_WENOZ, "wenoz2": I.RECON_WENOZ,
+             "minmod": I.RECON_MINMOD}[kind.split("-")[-1]]
+    prob = _instances_box(shift, precision, recon, 2 if kind.endswith("wenoz2") else 1)
+    G = H.G()
+    outs = {}
+    for tile in range(G.GRMHD_NTILE):
+        for sched in (G.GRMHD_SCHED_GRID, G.GRMHD_SCHED_QUEUE):
+            d = H.Dev(prob, tile=tile)
+            d.par.schedule = sched
+            d.step(2)
+            outs[(tile, sched)] = (H.interior_fields(prob, d.host(d.U)), H.interior_fields(prob, d.host(d.P)),
+                                   float(d.host(d.rate)[0]))
+    ref = outs[(3, G.GRMHD_SCHED_GRID)]
+    for key, (U, P, rate) in outs.items():
+        np.testing.assert_array_equal(U, ref[0], err_msg=f"{kind} tile/schedule {key} U")
+        np.testing.assert_array_equal(P, ref[1], err_msg=f"{kind} tile/schedule {key} P")
+        assert rate == ref[2], key
+
+
 @pytest.mark.parametrize("p_current", [0, 1])
 @pytest.mark.parametrize("tile", [0, 1, 2, 3])
 def test_queue_schedule_bitwise(tile, p_current):
