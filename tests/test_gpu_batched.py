@@ -122,24 +122,27 @@ def _instances_box(shift, precision, recon, wenoz_p=1):
 
 
 @pytest.mark.parametrize("kind", ["shift-fp64-weno5", "noshift-mixed-weno5", "shift-mixed-wenoz", "noshift-fp64-wenoz2",
-                                  "noshift-mixed-minmod"])
+                                  "noshift-mixed-minmod", "shift-fp64-weno5-rk4", "noshift-mixed-weno5-rk4"])
 def test_every_instance_agrees_bitwise(kind):
-    """Every tile shape and schedule computes the same face numbers, so two SSPRK3
-    steps agree bit for bit with the default tile's grid launch: this checks
-    each compiled stage-kernel instance (shifted metric, FP32 faces, WENO-Z
-    with p = 2) against the one the parity tests compare with the oracle."""
-    shift = kind.startswith("shift")
-    precision = I.PREC_MIXED if "mixed" in kind else I.PREC_FP64
+    """Every tile shape and schedule computes the same face numbers, so two steps
+    (SSPRK3, or classic RK4 with its step accumulator) agree bit for bit with
+    the default tile's grid launch: this checks each compiled stage-kernel
+    instance (shifted metric, FP32 faces, WENO-Z with p = 2) against the one the
+    parity tests compare with the oracle."""
+    parts = kind.split("-")
+    shift = parts[0] == "shift"
+    precision = I.PREC_MIXED if parts[1] == "mixed" else I.PREC_FP64
     recon = {"weno5": I.RECON_WENO5, "wenoz": I.RECON_WENOZ, "wenoz2": I.RECON_WENOZ,
-             "minmod": I.RECON_MINMOD}[kind.split("-")[-1]]
-    prob = _instances_box(shift, precision, recon, 2 if kind.endswith("wenoz2") else 1)
+             "minmod": I.RECON_MINMOD}[parts[2]]
+    scheme = 2 if kind.endswith("rk4") else 0
+    prob = _instances_box(shift, precision, recon, 2 if parts[2] == "wenoz2" else 1)
     G = H.G()
     outs = {}
     for tile in range(G.GRMHD_NTILE):
         for sched in (G.GRMHD_SCHED_GRID, G.GRMHD_SCHED_QUEUE):
             d = H.Dev(prob, tile=tile)
             d.par.schedule = sched
-            d.step(2)
+            d.step(2, scheme=scheme)
             outs[(tile, sched)] = (H.interior_fields(prob, d.host(d.U)), H.interior_fields(prob, d.host(d.P)),
                                    float(d.host(d.rate)[0]))
     ref = outs[(3, G.GRMHD_SCHED_GRID)]
